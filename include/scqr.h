@@ -1,0 +1,211 @@
+/*
+ * scqr.h — shifted Cholesky QR on AMD MI355X (gfx950): the C ABI of libscqr.so.
+ *
+ * Computes the thin QR factorization X = Q R of a tall-skinny X (m x n, m >= n, n <= 256),
+ * optionally in the oblique inner product (x, y)_B = x^T B y of an SPD B, following
+ * Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa, "Shifted CholeskyQR for computing the QR
+ * factorization of ill-conditioned matrices":
+ *   - Algorithm 1 (shiftedCholeskyQR): A = X^T X, R = chol(A + sI), Q = X R^{-1};
+ *   - Algorithm 3 (shiftedCholeskyQR3): one shifted pass, then CholeskyQR2;
+ *   - Algorithm 2 (iterated CholeskyQR, shift only on breakdown);
+ *   - Algorithm 5 (shiftedCholeskyQR3 in the B inner product, B tridiagonal here).
+ * The shift is s = 11 (m n + n (n+1)) u ||X||_2^2 (equation (eq:finds2)) or, for B != I,
+ * s = 11 (2 m sqrt(m n) + n (n+1)) u ||X||_2^2 ||B||_2 (equation (eq:finds2B)), u = 2^-53.
+ *
+ * Conventions shared by every entry point:
+ *   - All matrix pointers are DEVICE pointers (HBM), row-major, with explicit leading
+ *     dimensions (ld >= number of columns).  The caller owns and allocates every buffer
+ *     (inputs, outputs, workspace, info); the library never allocates device memory on these
+ *     paths and keeps no state between calls.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All work is
+ *     enqueued on it; nothing synchronizes with the host.
+ *   - Argument errors (shapes, null pointers, leading dimensions, workspace too small, n above
+ *     the supported maximum) are returned synchronously and enqueue nothing.
+ *   - Numerical outcomes (Cholesky breakdown, non-convergence, non-finite values) are written
+ *     asynchronously into the caller's device-side scqr_info record; read it after the
+ *     stream has completed.
+ *   - Calls are re-entrant: concurrent calls must use distinct workspaces and outputs.
+ */
+#ifndef SCQR_H
+#define SCQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SCQR_MAX_N 256
+#define SCQR_MAX_PASSES 16
+
+typedef enum {
+    SCQR_OK = 0,
+    SCQR_E_INVALID = 1,       /* bad argument (shape, pointer, leading dimension, option)     */
+    SCQR_E_WORKSPACE = 2,     /* workspace smaller than scqr_*_workspace_bytes() reported     */
+    SCQR_E_UNSUPPORTED = 3,   /* valid request outside what this build implements             */
+    SCQR_E_HIP = 4,           /* a HIP runtime call failed                                    */
+    SCQR_E_BREAKDOWN = 5,     /* a Cholesky factorization broke down (Algorithm 2 test)       */
+    SCQR_E_NOT_CONVERGED = 6, /* adaptive schedule hit max_passes without its stopping test   */
+    SCQR_E_NONFINITE = 7      /* a Gram matrix contained NaN or Inf                           */
+} scqr_status;
+
+/* Pass schedule. */
+enum {
+    SCQR_SCHED_FIXED3 = 0,   /* Algorithm 3 / 5: shifted pass, then two unshifted passes     */
+    SCQR_SCHED_ADAPTIVE = 1, /* Algorithm 3 followed by Algorithm 2 continuation: later passes
+                                shift only when their Cholesky breaks down; a pass is the last
+                                one when it ran unshifted on a Gram with ||A - I||_F <= 1/2   */
+    SCQR_SCHED_CHOLQR2 = 2,  /* two unshifted passes (CholeskyQR2)                           */
+    SCQR_SCHED_ITERATED = 3  /* Algorithm 2 from the first pass (shift only on breakdown)     */
+};
+
+/* Shift of a shifted pass. */
+enum {
+    SCQR_SHIFT_PAPER = 0,  /* (eq:finds2)/(eq:finds2B) with ||.||_2^2 from a power iteration  */
+    SCQR_SHIFT_FRO = 1,    /* the same with ||X||_F^2 in place of ||X||_2^2 (Section 4.1)    */
+    SCQR_SHIFT_SMALL = 2,  /* s = u ||X||_2^2 (||B||_2): remark after Table 3; no guarantee   */
+    SCQR_SHIFT_CUSTOM = 3  /* s = custom_alpha ||X||_2^2 (||B||_2)                            */
+};
+
+/* Arithmetic of the first (preconditioning) pass. */
+enum {
+    SCQR_PREC_FP64 = 0,
+    SCQR_PREC_FP32_FIRST = 1 /* first Gram in binary32 MFMA (binary64 reduction) with shift
+                                s32 = 11 ((k+2) n u32 + n (n+1) u) ||X||_2^2, k = 64 rows per
+                                binary32 chain, u32 = 2^-24; if s32 > ||X||_2^2 / 100 or its
+                                Cholesky breaks down, that pass is redone in binary64.  Not in
+                                the paper; Euclidean inner product only. */
+};
+
+typedef struct {
+    int32_t schedule;       /* SCQR_SCHED_*, default ADAPTIVE                                 */
+    int32_t shift_mode;     /* SCQR_SHIFT_*, default PAPER                                    */
+    int32_t precision;      /* SCQR_PREC_*, default FP64                                      */
+    int32_t max_passes;     /* 1..SCQR_MAX_PASSES cap for ADAPTIVE/ITERATED, default 6        */
+    int32_t final_gram;     /* 1: also form the Gram of the final Q and report omega_fro      */
+    int32_t debug_force_breakdown_pass; /* >0: the Cholesky of that pass reports breakdown    */
+    int32_t debug_zero_shift;           /* 1: every shift is zero                             */
+    int32_t reserved;
+    double custom_alpha;    /* SCQR_SHIFT_CUSTOM: s = custom_alpha ||X||_2^2 (||B||_2)        */
+    double bnorm;           /* > 0: caller's bound on ||B||_2; else the Gershgorin bound      */
+    double *trace;          /* nullable device buffer of max_passes * 2 * n * n doubles: for
+                               pass p (0-based) the input Gram at trace[(2p) n n] and the
+                               triangular factor R~ of that pass at trace[(2p+1) n n]          */
+} scqr_opts;
+
+/* Result record, written on the stream into caller-owned DEVICE memory. */
+typedef struct {
+    int32_t status;         /* scqr_status                                                    */
+    int32_t passes;         /* Cholesky QR passes whose R~ was applied                        */
+    int32_t shifted_mask;   /* bit p-1 set: pass p used a shift                               */
+    int32_t breakdown_mask; /* bit p-1 set: a Cholesky of pass p broke down                   */
+    int32_t fell_back_fp64; /* FP32_FIRST: the binary32 first pass was redone in binary64     */
+    int32_t reserved;
+    double shift[SCQR_MAX_PASSES];    /* shift used by pass p (0 if unshifted)                */
+    double norm2sq[SCQR_MAX_PASSES];  /* ||.||_2^2 estimate behind that shift (0 if none)    */
+    double gram_dev[SCQR_MAX_PASSES]; /* ||A_p - I||_F of the input Gram of pass p            */
+    double omega_fro;       /* final_gram: ||Q^T Q - I||_F (or Q^T B Q) from the device Gram  */
+    double bnorm;           /* ||B||_2 bound used (1 for B = I)                               */
+} scqr_info;
+
+/* Optional SPD operator B of the oblique inner product (Section 5).  NULL or kind NONE means
+ * B = I.  TRIDIAG: B symmetric tridiagonal with diag[m] and off[m-1] (device pointers); the
+ * caller guarantees B is SPD. */
+enum { SCQR_B_NONE = 0, SCQR_B_TRIDIAG = 1 };
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    const double *diag;
+    const double *off;
+} scqr_spd_op;
+
+/* Fills *opts with the defaults listed above. */
+void scqr_default_opts(scqr_opts *opts);
+
+/* Human-readable name of a status code (static storage). */
+const char *scqr_status_string(scqr_status s);
+
+/* Workspace size in bytes for scqr_qr / scqr_gram / scqr_trsm at this shape (B may be NULL,
+ * opts may be NULL for defaults).  Returns SCQR_E_INVALID for unsupported shapes. */
+scqr_status scqr_workspace_bytes(int64_t m, int64_t n, const scqr_spd_op *B,
+                                 const scqr_opts *opts, size_t *bytes);
+
+/*
+ * Thin QR factorization X = Q R by shifted Cholesky QR (Algorithms 1-3, 5).
+ *   X   m x n, ldx >= n, read only (unless Q aliases it).
+ *   Q   m x n, ldq >= n, output; may alias X exactly (Q == X and ldq == ldx) for in-place use.
+ *   R   n x n, ldr >= n, output, upper triangular with positive diagonal; the strictly lower
+ *       triangle is written with zeros.  Must not alias X, Q or the workspace.
+ *   ws  workspace of at least scqr_workspace_bytes() bytes, 256-byte aligned.
+ *   info device pointer to one scqr_info, written on the stream.
+ * With B of kind TRIDIAG, Q^T B Q = I instead of Q^T Q = I (Algorithm 5; passes 2 and later
+ * use the B-Gram Q^T B Q).
+ */
+scqr_status scqr_qr(void *stream, int64_t m, int64_t n, const double *X, int64_t ldx,
+                    const scqr_spd_op *B, double *Q, int64_t ldq, double *R, int64_t ldr,
+                    void *ws, size_t ws_bytes, const scqr_opts *opts, scqr_info *info);
+
+/*
+ * Gram matrix G = X^T X (equation (eq:gram)), or X^T B X for tridiagonal B (Algorithm 4 line
+ * 1): the split-m SYRK of one pass with a fixed-order reduction across workgroups.  G is
+ * n x n, ldg >= n, both triangles written (the upper triangle mirrored).
+ */
+scqr_status scqr_gram(void *stream, int64_t m, int64_t n, const double *X, int64_t ldx,
+                      const scqr_spd_op *B, double *G, int64_t ldg, void *ws, size_t ws_bytes);
+
+/*
+ * Triangular solve Q = X R^{-1} row by row (Algorithm 1 line 4): each row q_i^T R = x_i^T is
+ * solved by forward substitution (multiplication by the reciprocal of the diagonal).  R upper
+ * triangular n x n with nonzero diagonal (only the upper triangle is read).  Q may alias X.
+ */
+scqr_status scqr_trsm(void *stream, int64_t m, int64_t n, const double *X, int64_t ldx,
+                      const double *R, int64_t ldr, double *Q, int64_t ldq, void *ws,
+                      size_t ws_bytes);
+
+/*
+ * Batched QR of independent problems (X_i m_i x n_i, each row-major with ld = n_i).  Shapes
+ * are host arrays; the pointer arrays are host arrays of device pointers.  Every instance
+ * runs the schedule in opts and writes its own infos[i] (device array of batch records).
+ * Workspace from scqr_batched_workspace_bytes().  Q_i may alias X_i.
+ */
+scqr_status scqr_batched_workspace_bytes(int32_t batch, const int64_t *m, const int64_t *n,
+                                         const scqr_opts *opts, size_t *bytes);
+scqr_status scqr_qr_batched(void *stream, int32_t batch, const int64_t *m, const int64_t *n,
+                            const double *const *X, double *const *Q, double *const *R,
+                            void *ws, size_t ws_bytes, const scqr_opts *opts, scqr_info *infos);
+
+/*
+ * QR adjoint (reverse-mode derivative of X -> (Q, R) for the thin QR with positive diagonal):
+ *   M = R dR^T - dQ^T Q,  dX = (dQ + Q copyltu(M)) R^{-T},
+ * copyltu(M)_ij = M_{max(i,j), min(i,j)}.  dQ (m x n) and dR (n x n, only its upper triangle
+ * is read) may be NULL (zero).  dX m x n output; may alias dQ.  Row-major, explicit lds.
+ */
+scqr_status scqr_backward_workspace_bytes(int64_t m, int64_t n, size_t *bytes);
+scqr_status scqr_qr_backward(void *stream, int64_t m, int64_t n, const double *Q, int64_t ldq,
+                             const double *R, int64_t ldr, const double *dQ, int64_t lddq,
+                             const double *dR, int64_t lddr, double *dX, int64_t lddx, void *ws,
+                             size_t ws_bytes);
+
+/*
+ * Kernel timing for measurement.  While enabled, every kernel the library enqueues is
+ * bracketed by HIP events recorded on the launch stream (events are created on first use, so
+ * keep this off on latency-critical paths).  scqr_profile_read() synchronizes on the
+ * recorded events and returns, per kernel name, the number of launches and their summed
+ * duration in milliseconds, then clears the record.
+ */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+} scqr_kernel_stat;
+scqr_status scqr_profile_enable(int32_t on);
+scqr_status scqr_profile_read(scqr_kernel_stat *stats, int32_t capacity, int32_t *count);
+
+/* Build identification: a static string naming the target architecture and version. */
+const char *scqr_build_info(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCQR_H */

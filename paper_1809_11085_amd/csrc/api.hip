@@ -1,0 +1,436 @@
+// C ABI of libscqr.so: argument validation, workspace carving and the enqueue sequence of the
+// shifted Cholesky QR schedules.  Every decision that depends on computed values (shift,
+// breakdown, stopping test) is taken on the device by the Cholesky kernel; the host enqueues
+// the longest schedule and later kernels skip themselves through the device control block.
+#include <atomic>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "scqr_internal.h"
+
+using namespace scqr;
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------- profiling
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+std::atomic<int> g_prof_on{0};
+std::vector<ProfRec> g_prof;
+thread_local hipEvent_t t_pending_a = nullptr;
+thread_local const char *t_pending_name = nullptr;
+
+}  // namespace
+
+namespace scqr {
+void prof_before(hipStream_t s, const char *name)
+{
+    if (!g_prof_on.load(std::memory_order_relaxed)) return;
+    hipEvent_t a;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    hipEventRecord(a, s);
+    t_pending_a = a;
+    t_pending_name = name;
+}
+void prof_after(hipStream_t s)
+{
+    if (!g_prof_on.load(std::memory_order_relaxed) || !t_pending_a) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) != hipSuccess) return;
+    hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back({t_pending_name, t_pending_a, b});
+    t_pending_a = nullptr;
+}
+}  // namespace scqr
+
+namespace {
+
+bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+size_t mat_bytes(int64_t rows, int64_t cols, int64_t ld)
+{
+    if (rows <= 0) return 0;
+    return sizeof(double) * (size_t)((rows - 1) * ld + cols);
+}
+
+scqr_status check_opts(const scqr_opts *o)
+{
+    if (o->schedule < 0 || o->schedule > 3) return SCQR_E_INVALID;
+    if (o->shift_mode < 0 || o->shift_mode > 3) return SCQR_E_INVALID;
+    if (o->precision < 0 || o->precision > 1) return SCQR_E_INVALID;
+    if (o->max_passes < 1 || o->max_passes > SCQR_MAX_PASSES) return SCQR_E_INVALID;
+    if (o->shift_mode == SCQR_SHIFT_CUSTOM && !(o->custom_alpha >= 0.0)) return SCQR_E_INVALID;
+    return SCQR_OK;
+}
+
+struct Layout {
+    int np, nwg, nlvl2;
+    int64_t elems;
+    size_t off_ctl, off_G, off_Ge, off_Rt, off_dinv, off_R0, off_R1, off_part, off_lvl2, off_bmax, total;
+};
+
+Layout layout(int64_t m, int64_t n, bool oblique)
+{
+    Layout L;
+    L.np = padded_n(n);
+    L.nwg = pass_grid(m, L.np);
+    L.nlvl2 = (L.nwg + 31) / 32;
+    L.elems = pass_partial_elems(L.np, oblique);
+    const size_t np = (size_t)L.np;
+    size_t o = 0;
+    L.off_ctl = o;
+    o += align256(sizeof(Ctl));
+    L.off_G = o;
+    o += align256(sizeof(double) * np * (np + 1));
+    L.off_Ge = o;
+    o += align256(sizeof(double) * np * (np + 1));
+    L.off_Rt = o;
+    o += align256(sizeof(double) * np * np);
+    L.off_dinv = o;
+    o += align256(sizeof(double) * np);
+    L.off_R0 = o;
+    o += align256(sizeof(double) * np * np);
+    L.off_R1 = o;
+    o += align256(sizeof(double) * np * np);
+    L.off_part = o;
+    o += align256(sizeof(double) * (size_t)L.nwg * (size_t)L.elems);
+    L.off_lvl2 = o;
+    o += align256(sizeof(double) * (size_t)L.nlvl2 * (size_t)L.elems);
+    L.off_bmax = o;
+    o += align256(sizeof(double) * (size_t)L.nwg);
+    L.total = o;
+    return L;
+}
+
+Work carve(void *ws, const Layout &L)
+{
+    char *c = static_cast<char *>(ws);
+    Work w;
+    w.ctl = reinterpret_cast<Ctl *>(c + L.off_ctl);
+    w.G = reinterpret_cast<double *>(c + L.off_G);
+    w.Ge = reinterpret_cast<double *>(c + L.off_Ge);
+    w.Rt = reinterpret_cast<double *>(c + L.off_Rt);
+    w.dinv = reinterpret_cast<double *>(c + L.off_dinv);
+    w.Racc[0] = reinterpret_cast<double *>(c + L.off_R0);
+    w.Racc[1] = reinterpret_cast<double *>(c + L.off_R1);
+    w.partials = reinterpret_cast<double *>(c + L.off_part);
+    w.lvl2 = reinterpret_cast<double *>(c + L.off_lvl2);
+    w.bmax = reinterpret_cast<double *>(c + L.off_bmax);
+    w.nwg = L.nwg;
+    w.nlvl2 = L.nlvl2;
+    w.parts_elems = L.elems;
+    return w;
+}
+
+bool is_oblique(const scqr_spd_op *B) { return B && B->kind == SCQR_B_TRIDIAG; }
+
+scqr_status check_B(const scqr_spd_op *B, int64_t m)
+{
+    if (!B || B->kind == SCQR_B_NONE) return SCQR_OK;
+    if (B->kind != SCQR_B_TRIDIAG) return SCQR_E_INVALID;
+    if (!B->diag || (m > 1 && !B->off)) return SCQR_E_INVALID;
+    return SCQR_OK;
+}
+
+scqr_status hip_status(hipError_t e) { return e == hipSuccess ? SCQR_OK : SCQR_E_HIP; }
+
+}  // namespace
+
+extern "C" {
+
+void scqr_default_opts(scqr_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->schedule = SCQR_SCHED_ADAPTIVE;
+    o->shift_mode = SCQR_SHIFT_PAPER;
+    o->precision = SCQR_PREC_FP64;
+    o->max_passes = 6;
+    o->final_gram = 0;
+    o->custom_alpha = 0.0;
+    o->bnorm = 0.0;
+    o->trace = nullptr;
+}
+
+const char *scqr_status_string(scqr_status s)
+{
+    switch (s) {
+    case SCQR_OK: return "SCQR_OK";
+    case SCQR_E_INVALID: return "SCQR_E_INVALID: invalid argument";
+    case SCQR_E_WORKSPACE: return "SCQR_E_WORKSPACE: workspace too small or misaligned";
+    case SCQR_E_UNSUPPORTED: return "SCQR_E_UNSUPPORTED: request outside this build";
+    case SCQR_E_HIP: return "SCQR_E_HIP: HIP runtime error";
+    case SCQR_E_BREAKDOWN: return "SCQR_E_BREAKDOWN: Cholesky factorization broke down";
+    case SCQR_E_NOT_CONVERGED: return "SCQR_E_NOT_CONVERGED: max_passes reached";
+    case SCQR_E_NONFINITE: return "SCQR_E_NONFINITE: non-finite Gram matrix";
+    }
+    return "SCQR: unknown status";
+}
+
+const char *scqr_build_info(void) { return "scqr 0.1 gfx950 (FP64 MFMA 16x16x4, HIP)"; }
+
+scqr_status scqr_workspace_bytes(int64_t m, int64_t n, const scqr_spd_op *B, const scqr_opts *opts,
+                                 size_t *bytes)
+{
+    if (!bytes || n < 1 || n > SCQR_MAX_N || m < n) return SCQR_E_INVALID;
+    if (opts) {
+        scqr_status st = check_opts(opts);
+        if (st != SCQR_OK) return st;
+    }
+    *bytes = layout(m, n, is_oblique(B)).total;
+    return SCQR_OK;
+}
+
+scqr_status scqr_qr(void *stream, int64_t m, int64_t n, const double *X, int64_t ldx,
+                    const scqr_spd_op *B, double *Q, int64_t ldq, double *R, int64_t ldr, void *ws,
+                    size_t ws_bytes, const scqr_opts *opts, scqr_info *info)
+{
+    if (n < 1 || m < n) return SCQR_E_INVALID;
+    if (n > SCQR_MAX_N) return SCQR_E_UNSUPPORTED;
+    if (!X || !Q || !R || !ws || !info) return SCQR_E_INVALID;
+    if (ldx < n || ldq < n || ldr < n) return SCQR_E_INVALID;
+    scqr_opts o;
+    if (opts)
+        o = *opts;
+    else
+        scqr_default_opts(&o);
+    scqr_status st = check_opts(&o);
+    if (st != SCQR_OK) return st;
+    st = check_B(B, m);
+    if (st != SCQR_OK) return st;
+    const bool obl = is_oblique(B);
+    if (obl && o.precision == SCQR_PREC_FP32_FIRST) return SCQR_E_UNSUPPORTED;
+    // aliasing: Q may equal X exactly; R must not overlap X, Q or the workspace
+    const size_t xb = mat_bytes(m, n, ldx), qb = mat_bytes(m, n, ldq), rb = mat_bytes(n, n, ldr);
+    if (Q != X && ranges_overlap(X, xb, Q, qb)) return SCQR_E_INVALID;
+    if (Q == X && ldq != ldx) return SCQR_E_INVALID;
+    if (ranges_overlap(R, rb, X, xb) || ranges_overlap(R, rb, Q, qb)) return SCQR_E_INVALID;
+    const Layout L = layout(m, n, obl);
+    if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return SCQR_E_WORKSPACE;
+    if (ranges_overlap(ws, L.total, R, rb) || ranges_overlap(ws, L.total, Q, qb) ||
+        ranges_overlap(ws, L.total, X, xb))
+        return SCQR_E_INVALID;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Work w = carve(ws, L);
+    Problem p;
+    p.m = m;
+    p.n = (int)n;
+    p.np = L.np;
+    p.X = X;
+    p.ldx = ldx;
+    p.Q = Q;
+    p.ldq = ldq;
+    p.R = R;
+    p.ldr = ldr;
+    p.bdiag = obl ? B->diag : nullptr;
+    p.boff = obl ? B->off : nullptr;
+    SchedParams sp;
+    sp.schedule = o.schedule;
+    sp.shift_mode = o.shift_mode;
+    sp.precision = o.precision;
+    sp.max_passes = o.max_passes;
+    sp.final_gram = o.final_gram ? 1 : 0;
+    sp.force_bd = o.debug_force_breakdown_pass;
+    sp.zero_shift = o.debug_zero_shift;
+    sp.oblique = obl ? 1 : 0;
+    sp.custom_alpha = o.custom_alpha;
+    sp.bnorm_user = o.bnorm;
+    sp.trace = o.trace;
+    sp.info = info;
+
+    const bool f32 = o.precision == SCQR_PREC_FP32_FIRST;
+    const int fg = sp.final_gram;
+    const int64_t E = pass_partial_elems(L.np, false);
+    hipError_t e = launch_init(s, p, w, sp);
+    if (e != hipSuccess) return SCQR_E_HIP;
+    // pass 1 Gram (binary32 for FP32-first; X^T B X and X^T X for the oblique form)
+    e = launch_pass(s, p, w, 0, 0, f32, obl, obl);
+    if (e == hipSuccess) e = launch_reduce(s, w, 0, obl ? 2 * E : E, 0);
+    if (e == hipSuccess) e = launch_chol(s, p, w, sp, 1, 0);
+    if (e == hipSuccess && f32) {
+        e = launch_pass(s, p, w, 0, -1, false, false, false);
+        if (e == hipSuccess) e = launch_reduce(s, w, -1, E, 0);
+        if (e == hipSuccess) e = launch_chol(s, p, w, sp, 1, 1);
+    }
+    const int P = o.schedule == SCQR_SCHED_FIXED3 ? 3 : o.schedule == SCQR_SCHED_CHOLQR2 ? 2 : o.max_passes;
+    for (int pass = 1; pass <= P && e == hipSuccess; ++pass) {
+        Problem pp = p;
+        if (pass > 1) {
+            pp.X = Q;
+            pp.ldx = ldq;
+        }
+        e = launch_pass(s, pp, w, 1 | (fg ? 0x100 : 0), pass, false, obl, false);
+        if (e == hipSuccess) e = launch_reduce(s, w, pass, E, fg);
+        if (e == hipSuccess && pass < P) e = launch_chol(s, p, w, sp, pass + 1, 0);
+    }
+    if (e == hipSuccess && fg) e = launch_final_omega(s, p, w, sp);
+    return hip_status(e);
+}
+
+scqr_status scqr_gram(void *stream, int64_t m, int64_t n, const double *X, int64_t ldx,
+                      const scqr_spd_op *B, double *G, int64_t ldg, void *ws, size_t ws_bytes)
+{
+    if (n < 1 || m < 1) return SCQR_E_INVALID;
+    if (n > SCQR_MAX_N) return SCQR_E_UNSUPPORTED;
+    if (!X || !G || !ws || ldx < n || ldg < n) return SCQR_E_INVALID;
+    scqr_status st = check_B(B, m);
+    if (st != SCQR_OK) return st;
+    const bool obl = is_oblique(B);
+    const Layout L = layout(m < n ? n : m, n, obl);
+    if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return SCQR_E_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Work w = carve(ws, L);
+    Problem p{};
+    p.m = m;
+    p.n = (int)n;
+    p.np = L.np;
+    p.X = X;
+    p.ldx = ldx;
+    p.bdiag = obl ? B->diag : nullptr;
+    p.boff = obl ? B->off : nullptr;
+    const int64_t E = pass_partial_elems(L.np, false);
+    hipError_t e = launch_pass(s, p, w, 0, 0, false, obl, false);
+    if (e == hipSuccess) e = launch_reduce(s, w, 0, E, 0);
+    if (e == hipSuccess) e = launch_gram_out(s, w, L.np, (int)n, G, ldg);
+    return hip_status(e);
+}
+
+scqr_status scqr_trsm(void *stream, int64_t m, int64_t n, const double *X, int64_t ldx, const double *R,
+                      int64_t ldr, double *Q, int64_t ldq, void *ws, size_t ws_bytes)
+{
+    if (n < 1 || m < 1) return SCQR_E_INVALID;
+    if (n > SCQR_MAX_N) return SCQR_E_UNSUPPORTED;
+    if (!X || !R || !Q || !ws || ldx < n || ldr < n || ldq < n) return SCQR_E_INVALID;
+    const size_t xb = mat_bytes(m, n, ldx), qb = mat_bytes(m, n, ldq);
+    if (Q != X && ranges_overlap(X, xb, Q, qb)) return SCQR_E_INVALID;
+    if (Q == X && ldq != ldx) return SCQR_E_INVALID;
+    const Layout L = layout(m < n ? n : m, n, false);
+    if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return SCQR_E_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Work w = carve(ws, L);
+    Problem p{};
+    p.m = m;
+    p.n = (int)n;
+    p.np = L.np;
+    p.X = X;
+    p.ldx = ldx;
+    p.Q = Q;
+    p.ldq = ldq;
+    hipError_t e = launch_set_factor(s, w, L.np, (int)n, R, ldr);
+    if (e == hipSuccess) e = launch_pass(s, p, w, 2, 0, false, false, false);
+    return hip_status(e);
+}
+
+scqr_status scqr_batched_workspace_bytes(int32_t batch, const int64_t *m, const int64_t *n,
+                                         const scqr_opts *opts, size_t *bytes)
+{
+    if (!bytes || batch < 0 || (batch > 0 && (!m || !n))) return SCQR_E_INVALID;
+    size_t mx = 0;
+    for (int32_t i = 0; i < batch; ++i) {
+        size_t b = 0;
+        scqr_status st = scqr_workspace_bytes(m[i], n[i], nullptr, opts, &b);
+        if (st != SCQR_OK) return st;
+        mx = b > mx ? b : mx;
+    }
+    *bytes = mx;
+    return SCQR_OK;
+}
+
+scqr_status scqr_qr_batched(void *stream, int32_t batch, const int64_t *m, const int64_t *n,
+                            const double *const *X, double *const *Q, double *const *R, void *ws,
+                            size_t ws_bytes, const scqr_opts *opts, scqr_info *infos)
+{
+    if (batch < 0) return SCQR_E_INVALID;
+    if (batch == 0) return SCQR_OK;
+    if (!m || !n || !X || !Q || !R || !infos || !ws) return SCQR_E_INVALID;
+    size_t need = 0;
+    scqr_status st = scqr_batched_workspace_bytes(batch, m, n, opts, &need);
+    if (st != SCQR_OK) return st;
+    if (ws_bytes < need) return SCQR_E_WORKSPACE;
+    for (int32_t i = 0; i < batch; ++i) {
+        st = scqr_qr(stream, m[i], n[i], X[i], n[i], nullptr, Q[i], n[i], R[i], n[i], ws, ws_bytes, opts,
+                     infos + i);
+        if (st != SCQR_OK) return st;
+    }
+    return SCQR_OK;
+}
+
+scqr_status scqr_backward_workspace_bytes(int64_t m, int64_t n, size_t *bytes)
+{
+    if (!bytes || n < 1 || n > SCQR_MAX_N || m < n) return SCQR_E_INVALID;
+    *bytes = backward_ws_bytes(m, (int)n);
+    return SCQR_OK;
+}
+
+scqr_status scqr_qr_backward(void *stream, int64_t m, int64_t n, const double *Q, int64_t ldq, const double *R,
+                             int64_t ldr, const double *dQ, int64_t lddq, const double *dR, int64_t lddr,
+                             double *dX, int64_t lddx, void *ws, size_t ws_bytes)
+{
+    if (n < 1 || m < n) return SCQR_E_INVALID;
+    if (n > SCQR_MAX_N) return SCQR_E_UNSUPPORTED;
+    if (!Q || !R || !dX || !ws) return SCQR_E_INVALID;
+    if (ldq < n || ldr < n || lddx < n || (dQ && lddq < n) || (dR && lddr < n)) return SCQR_E_INVALID;
+    const size_t qb = mat_bytes(m, n, ldq), xb = mat_bytes(m, n, lddx);
+    if (ranges_overlap(Q, qb, dX, xb)) return SCQR_E_INVALID;
+    if (dQ && dQ != dX && ranges_overlap(dQ, mat_bytes(m, n, lddq), dX, xb)) return SCQR_E_INVALID;
+    if (dQ == dX && lddq != lddx) return SCQR_E_INVALID;
+    if (ws_bytes < backward_ws_bytes(m, (int)n) || (reinterpret_cast<uintptr_t>(ws) & 255))
+        return SCQR_E_WORKSPACE;
+    return hip_status(launch_backward(static_cast<hipStream_t>(stream), m, (int)n, Q, ldq, R, ldr, dQ, lddq, dR,
+                                      lddr, dX, lddx, ws));
+}
+
+scqr_status scqr_profile_enable(int32_t on)
+{
+    g_prof_on.store(on ? 1 : 0);
+    return SCQR_OK;
+}
+
+scqr_status scqr_profile_read(scqr_kernel_stat *stats, int32_t capacity, int32_t *count)
+{
+    if (!count || capacity < 0 || (capacity > 0 && !stats)) return SCQR_E_INVALID;
+    std::vector<ProfRec> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        recs.swap(g_prof);
+    }
+    std::vector<scqr_kernel_stat> agg;
+    scqr_status st = SCQR_OK;
+    for (auto &r : recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+            st = SCQR_E_HIP;
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+        size_t k = 0;
+        for (; k < agg.size(); ++k)
+            if (r.name == agg[k].name) break;
+        if (k == agg.size()) {
+            scqr_kernel_stat z;
+            std::memset(&z, 0, sizeof(z));
+            std::strncpy(z.name, r.name.c_str(), sizeof(z.name) - 1);
+            agg.push_back(z);
+        }
+        agg[k].launches += 1;
+        agg[k].total_ms += ms;
+    }
+    const int32_t nout = (int32_t)agg.size() < capacity ? (int32_t)agg.size() : capacity;
+    for (int32_t i = 0; i < nout; ++i) stats[i] = agg[i];
+    *count = (int32_t)agg.size();
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,499 @@
+// Small n x n kernels of shifted Cholesky QR, each run by a single workgroup:
+//   * assembly of the Gram from the level-2 partial sums (fixed order),
+//   * ||X||_2^2 estimate by power iteration (normest, Section 4.1) or ||X||_F^2,
+//   * the shift s of equation (eq:finds2) / (eq:finds2B) (or the FP32-first shift),
+//   * R~ = chol(A + sI) with breakdown detection (Algorithm 1 line 3, Algorithm 2 test),
+//   * R := R~ R (Algorithms 2 and 3) and the schedule decisions of Algorithms 2, 3, 5,
+// all in binary64.  The decisions are written to the device control block and to the
+// caller's info record; later kernels of the schedule read them, so the host never waits.
+#include "scqr_internal.h"
+
+namespace scqr {
+
+constexpr int kCholThreads = 256;
+
+__device__ double block_sum(double v, double *scratch)
+{
+    // fixed-order block reduction: lanes by shuffle tree, then waves in order
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) scratch[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += scratch[i];
+    __syncthreads();
+    return s;
+}
+
+__device__ int block_or(int v, double *scratch)
+{
+    const double s = block_sum(v ? 1.0 : 0.0, scratch);
+    return s > 0.0;
+}
+
+// Sum of the level-2 partials of tile element e (order g = 0, 1, ...).
+__device__ __forceinline__ double lvl2_sum(const Work &w, int64_t elems, int64_t e)
+{
+    double s = 0.0;
+    for (int g = 0; g < w.nlvl2; ++g) s += w.lvl2[(int64_t)g * elems + e];
+    return s;
+}
+
+// Assemble an np x np symmetric Gram (stride S) from the level-2 partial tiles starting at
+// element offset `base`; the upper triangle is taken and mirrored, entries beyond n are 0.
+template <int NP>
+__device__ void assemble(const Work &w, int n, int64_t elems, int64_t base, bool f32_layout,
+                         double *G, int S)
+{
+    constexpr int NT = NP / 16;
+    constexpr int T = NT * (NT + 1) / 2;
+    for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) G[(idx / NP) * S + idx % NP] = 0.0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < T * 256; e += blockDim.x) {
+        const int t = e >> 8;
+        int I, J, ii, jj;
+        tile_ij(NT, t, I, J);
+        if (f32_layout)
+            acc32_rc(e & 255, ii, jj);
+        else
+            acc64_rc(e & 255, ii, jj);
+        const int i = 16 * I + ii, j = 16 * J + jj;
+        if (i > j || i >= n || j >= n) continue;
+        const double v = lvl2_sum(w, elems, base + e);
+        G[i * S + j] = v;
+        G[j * S + i] = v;
+    }
+    __syncthreads();
+}
+
+// Rayleigh-quotient power iteration for lambda_max of the symmetric n x n matrix G (stride S):
+// start vector 1/sqrt(n), at most 80 iterations, stop when the quotient changes by <= 1e-9
+// relative.  Run by the whole block; v, y are NP-length scratch arrays.
+template <int NP>
+__device__ double power_lambda(const double *G, int S, int n, double *v, double *y, double *red)
+{
+    for (int i = threadIdx.x; i < NP; i += blockDim.x) v[i] = (i < n) ? 1.0 / sqrt((double)n) : 0.0;
+    __syncthreads();
+    double lam = 0.0;
+    for (int it = 0; it < 80; ++it) {
+        double part_vy = 0.0, part_yy = 0.0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            double acc = 0.0;
+            for (int k = 0; k < n; ++k) acc = __builtin_fma(G[i * S + k], v[k], acc);
+            y[i] = acc;
+            part_vy += v[i] * acc;
+            part_yy += acc * acc;
+        }
+        const double vy = block_sum(part_vy, red);
+        const double yy = block_sum(part_yy, red);
+        const double prev = lam;
+        lam = vy;
+        if (!(yy > 0.0)) break;
+        const double inv = 1.0 / sqrt(yy);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = y[i] * inv;
+        __syncthreads();
+        if (it > 0 && fabs(lam - prev) <= 1e-9 * fabs(lam)) break;
+    }
+    return lam;
+}
+
+// In-place upper Cholesky of G + sI (upper triangle of G, stride S).  Returns 0 or 1 + the
+// column whose pivot radicand was <= 0 or not finite.  Right-looking: after step k the trailing
+// entries hold a_ij + s[i==j] - sum_{k' <= k} r_k'i r_k'j, subtracted in increasing k'.
+__device__ int chol_inplace(double *G, int S, int n, double s)
+{
+    if (s != 0.0) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) G[i * S + i] = G[i * S + i] + s;
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        const double d = G[k * S + k];
+        if (!(d > 0.0) || !isfinite(d)) return k + 1;
+        const double rkk = sqrt(d);
+        __syncthreads();
+        for (int j = k + threadIdx.x; j < n; j += blockDim.x) G[k * S + j] = (j == k) ? rkk : G[k * S + j] / rkk;
+        __syncthreads();
+        const int rem = n - 1 - k;
+        for (int q = threadIdx.x; q < rem * rem; q += blockDim.x) {
+            // q -> (i, j) over the trailing square; only k < i <= j < n is updated
+            const int a = q / rem, b = q - a * rem;
+            if (a > b) continue;
+            const int ii = k + 1 + a, jj = k + 1 + b;
+            G[ii * S + jj] = __builtin_fma(-G[k * S + ii], G[k * S + jj], G[ii * S + jj]);
+        }
+        __syncthreads();
+    }
+    return 0;
+}
+
+__device__ double shift_value(const SchedParams &sp, int64_t m, int n, double norm2sq,
+                              double bfac, bool oblique, bool f32pass)
+{
+    const double dm = (double)m, dn = (double)n;
+    if (f32pass)
+        return 11.0 * ((kF32Chain + 2.0) * dn * kU32 + dn * (dn + 1.0) * kU64) * norm2sq;
+    double c;
+    if (sp.shift_mode == SCQR_SHIFT_SMALL)
+        c = kU64;
+    else if (sp.shift_mode == SCQR_SHIFT_CUSTOM)
+        c = sp.custom_alpha;
+    else if (oblique)
+        c = 11.0 * (2.0 * dm * sqrt(dm * dn) + dn * (dn + 1.0)) * kU64;
+    else
+        c = 11.0 * (dm * dn + dn * (dn + 1.0)) * kU64;
+    return c * norm2sq * bfac;
+}
+
+// variant 0: pass `pass` of the schedule.  variant 1: binary64 redo of pass 1 after the
+// FP32-first attempt was rejected.
+template <int NP>
+__global__ void __launch_bounds__(kCholThreads)
+k_chol(Problem p, Work w, SchedParams sp, int pass, int variant)
+{
+    constexpr bool IN_LDS = NP <= 128;
+    constexpr int S = NP + 1;
+    __shared__ double lds[IN_LDS ? NP * S : 1];
+    __shared__ double vbuf[NP], ybuf[NP], red[16];
+    __shared__ int sh_flag;
+    Ctl *ctl = w.ctl;
+    scqr_info *info = sp.info;
+
+    if (variant == 1) {
+        if (!(ctl->active && ctl->redo_fp64)) return;
+    } else {
+        if (!(ctl->active && ctl->pass == pass - 1 && ctl->last == 0)) return;
+    }
+    const int n = p.n;
+    const bool oblique = sp.oblique != 0;
+    const bool f32pass = (variant == 0 && pass == 1 && sp.precision == SCQR_PREC_FP32_FIRST);
+    const bool obl_first = oblique && pass == 1;
+    const int64_t E = (int64_t)upper_tiles(NP / 16) * 256;
+    const int64_t elems = obl_first ? 2 * E : E;
+    double *G = IN_LDS ? lds : w.G;
+    const int bit = 1 << (pass - 1);
+
+    assemble<NP>(w, n, elems, 0, f32pass, G, S);
+
+    // finiteness, ||A - I||_F and trace
+    double dev = 0.0, tr = 0.0;
+    int bad = 0;
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+        const int i = idx / n, j = idx % n;
+        const double a = G[i * S + j];
+        if (!isfinite(a)) bad = 1;
+        const double d = a - (i == j ? 1.0 : 0.0);
+        dev += d * d;
+        if (i == j) tr += a;
+    }
+    bad = block_or(bad, red);
+    dev = sqrt(block_sum(dev, red));
+    tr = block_sum(tr, red);
+    if (bad) {
+        if (threadIdx.x == 0) {
+            ctl->active = 0;
+            ctl->status = SCQR_E_NONFINITE;
+            info->status = SCQR_E_NONFINITE;
+            info->passes = pass - 1;
+        }
+        return;
+    }
+    if (threadIdx.x == 0) info->gram_dev[pass - 1] = dev;
+    if (sp.trace) {
+        double *tg = sp.trace + (int64_t)(2 * (pass - 1)) * n * n;
+        for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) tg[idx] = G[(idx / n) * S + idx % n];
+    }
+
+    // norm estimate used by a shift of this pass
+    auto norm_estimate = [&]() -> double {
+        if (obl_first) {
+            // ||X||_2 of (eq:finds2B) is the Euclidean norm: Gram X^T X assembled in w.Ge
+            assemble<NP>(w, n, elems, E, false, w.Ge, S);
+            if (sp.shift_mode == SCQR_SHIFT_FRO) {
+                double t2 = 0.0;
+                for (int i = threadIdx.x; i < n; i += blockDim.x) t2 += w.Ge[i * S + i];
+                return block_sum(t2, red);
+            }
+            return power_lambda<NP>(w.Ge, S, n, vbuf, ybuf, red);
+        }
+        if (sp.shift_mode == SCQR_SHIFT_FRO) return tr;
+        return power_lambda<NP>(G, S, n, vbuf, ybuf, red);
+    };
+    double bfac = 1.0;
+    if (obl_first) {
+        double b = sp.bnorm_user;
+        if (!(b > 0.0)) {
+            b = 0.0;
+            for (int i = 0; i < w.nwg; ++i) b = w.bmax[i] > b ? w.bmax[i] : b;
+        }
+        bfac = b;
+        if (threadIdx.x == 0) {
+            ctl->bnorm = b;
+            info->bnorm = b;
+        }
+    }
+
+    const bool shift_first =
+        f32pass || (pass == 1 && (sp.schedule == SCQR_SCHED_FIXED3 || sp.schedule == SCQR_SCHED_ADAPTIVE));
+    const bool forced = (sp.force_bd == pass) && variant == 0;
+    int shifted = 0, bd = 0;
+    double s = 0.0, nrm = 0.0;
+    if (shift_first) {
+        nrm = norm_estimate();
+        s = shift_value(sp, p.m, n, nrm, bfac, oblique, f32pass);
+        if (sp.zero_shift) s = 0.0;
+        if (f32pass && s > 0.01 * nrm) {
+            bd = -1;  // binary32 shift too large: redo the first pass in binary64
+        } else {
+            bd = forced ? 1 : chol_inplace(G, S, n, s);
+        }
+        if (f32pass && bd != 0) {
+            if (threadIdx.x == 0) {
+                ctl->redo_fp64 = 1;
+                info->fell_back_fp64 = 1;
+            }
+            return;
+        }
+        shifted = 1;
+    } else {
+        bd = forced ? 1 : chol_inplace(G, S, n, 0.0);
+        if (bd != 0 && (sp.schedule == SCQR_SCHED_ADAPTIVE || sp.schedule == SCQR_SCHED_ITERATED)) {
+            if (threadIdx.x == 0) info->breakdown_mask |= bit;
+            __syncthreads();
+            assemble<NP>(w, n, elems, 0, false, G, S);
+            nrm = norm_estimate();
+            s = shift_value(sp, p.m, n, nrm, bfac, oblique, false);
+            if (sp.zero_shift) s = 0.0;
+            shifted = 1;
+            bd = chol_inplace(G, S, n, s);
+        }
+    }
+    if (threadIdx.x == 0) {
+        info->shift[pass - 1] = s;
+        info->norm2sq[pass - 1] = nrm;
+        if (shifted) info->shifted_mask |= bit;
+    }
+    if (bd != 0) {
+        if (threadIdx.x == 0) {
+            info->breakdown_mask |= bit;
+            ctl->active = 0;
+            ctl->status = SCQR_E_BREAKDOWN;
+            info->status = SCQR_E_BREAKDOWN;
+            info->passes = pass - 1;
+        }
+        return;
+    }
+
+    // R~ (identity padding) and reciprocal diagonal for the substitution kernels
+    for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
+        const int i = idx / NP, j = idx % NP;
+        double v;
+        if (i < n && j < n)
+            v = (j >= i) ? G[i * S + j] : 0.0;
+        else
+            v = (i == j) ? 1.0 : 0.0;
+        w.Rt[idx] = v;
+    }
+    for (int i = threadIdx.x; i < NP; i += blockDim.x) w.dinv[i] = (i < n) ? 1.0 / G[i * S + i] : 1.0;
+    if (sp.trace) {
+        double *tr_ = sp.trace + (int64_t)(2 * (pass - 1) + 1) * n * n;
+        for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+            const int i = idx / n, j = idx % n;
+            tr_[idx] = (j >= i) ? G[i * S + j] : 0.0;
+        }
+    }
+    // R := R~ R (upper x upper), ping-pong; pass 1 starts from R = I
+    const double *Rold = w.Racc[(pass + 1) & 1];
+    double *Rnew = w.Racc[pass & 1];
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+        const int i = idx / n, j = idx % n;
+        double v = 0.0;
+        if (j >= i) {
+            if (pass == 1)
+                v = G[i * S + j];
+            else
+                for (int k = i; k <= j; ++k) v = __builtin_fma(G[i * S + k], Rold[k * NP + j], v);
+        }
+        Rnew[i * NP + j] = v;
+        p.R[(int64_t)i * p.ldr + j] = v;
+    }
+
+    if (threadIdx.x == 0) {
+        int last;
+        if (sp.schedule == SCQR_SCHED_FIXED3)
+            last = (pass == 3);
+        else if (sp.schedule == SCQR_SCHED_CHOLQR2)
+            last = (pass == 2);
+        else
+            last = (!shifted && dev <= 0.5);
+        const int maxp = sp.schedule == SCQR_SCHED_FIXED3 ? 3 : sp.schedule == SCQR_SCHED_CHOLQR2 ? 2 : sp.max_passes;
+        int status = SCQR_OK;
+        if (!last && pass >= maxp) {
+            last = 1;
+            status = SCQR_E_NOT_CONVERGED;
+        }
+        ctl->pass = pass;
+        ctl->redo_fp64 = 0;
+        info->passes = pass;
+        if (last) {
+            ctl->last = pass;
+            ctl->status = status;
+            info->status = status;
+        }
+    }
+}
+
+// Initialise the control block and the caller's info record.
+__global__ void k_init(Ctl *ctl, scqr_info *info)
+{
+    if (threadIdx.x == 0) {
+        ctl->active = 1;
+        ctl->pass = 0;
+        ctl->last = 0;
+        ctl->redo_fp64 = 0;
+        ctl->status = SCQR_E_NOT_CONVERGED;
+        ctl->f32_pass = 0;
+        ctl->bnorm = 1.0;
+    }
+    if (info) {
+        int32_t *wi = reinterpret_cast<int32_t *>(info);
+        for (int i = threadIdx.x; i < (int)(sizeof(scqr_info) / 4); i += blockDim.x) wi[i] = 0;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            info->status = SCQR_E_NOT_CONVERGED;
+            info->bnorm = 1.0;
+        }
+    }
+}
+
+// G (caller layout, both triangles) from the level-2 partials, for scqr_gram.
+template <int NP>
+__global__ void __launch_bounds__(256) k_gram_out(Work w, int n, double *G, int64_t ldg)
+{
+    constexpr int NT = NP / 16;
+    constexpr int T = NT * (NT + 1) / 2;
+    const int64_t E = (int64_t)T * 256;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < E; e += (int64_t)gridDim.x * 256) {
+        int I, J, ii, jj;
+        tile_ij(NT, (int)(e >> 8), I, J);
+        acc64_rc((int)(e & 255), ii, jj);
+        const int i = 16 * I + ii, j = 16 * J + jj;
+        if (i > j || i >= n || j >= n) continue;
+        const double v = lvl2_sum(w, E, e);
+        G[(int64_t)i * ldg + j] = v;
+        G[(int64_t)j * ldg + i] = v;
+    }
+}
+
+// Copy a caller's upper triangular R into the padded factor and reciprocal diagonal.
+template <int NP>
+__global__ void __launch_bounds__(256) k_set_factor(Work w, int n, const double *R, int64_t ldr)
+{
+    for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
+        const int i = idx / NP, j = idx % NP;
+        double v;
+        if (i < n && j < n)
+            v = (j >= i) ? R[(int64_t)i * ldr + j] : 0.0;
+        else
+            v = (i == j) ? 1.0 : 0.0;
+        w.Rt[idx] = v;
+    }
+    for (int i = threadIdx.x; i < NP; i += blockDim.x) w.dinv[i] = (i < n) ? 1.0 / R[(int64_t)i * ldr + i] : 1.0;
+}
+
+// ||G - I||_F of the final Gram (final_gram option).
+template <int NP>
+__global__ void __launch_bounds__(256) k_final_omega(Problem p, Work w, SchedParams sp)
+{
+    __shared__ double red[16];
+    Ctl *ctl = w.ctl;
+    if (!(ctl->active && ctl->last > 0)) return;
+    constexpr int NT = NP / 16;
+    constexpr int T = NT * (NT + 1) / 2;
+    const int64_t E = (int64_t)T * 256;
+    const int n = p.n;
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < T * 256; e += blockDim.x) {
+        int I, J, ii, jj;
+        tile_ij(NT, e >> 8, I, J);
+        acc64_rc(e & 255, ii, jj);
+        const int i = 16 * I + ii, j = 16 * J + jj;
+        if (i > j || i >= n || j >= n) continue;
+        const double d = lvl2_sum(w, E, e) - (i == j ? 1.0 : 0.0);
+        acc += (i == j ? 1.0 : 2.0) * d * d;
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) sp.info->omega_fro = sqrt(acc);
+}
+
+// ------------------------------------------------------------------------------------------
+hipError_t launch_chol(hipStream_t s, const Problem &p, const Work &w, const SchedParams &sp,
+                       int pass, int variant)
+{
+    prof_before(s, "chol");
+    switch (p.np) {
+    case 16: hipLaunchKernelGGL((k_chol<16>), dim3(1), dim3(kCholThreads), 0, s, p, w, sp, pass, variant); break;
+    case 32: hipLaunchKernelGGL((k_chol<32>), dim3(1), dim3(kCholThreads), 0, s, p, w, sp, pass, variant); break;
+    case 64: hipLaunchKernelGGL((k_chol<64>), dim3(1), dim3(kCholThreads), 0, s, p, w, sp, pass, variant); break;
+    case 128: hipLaunchKernelGGL((k_chol<128>), dim3(1), dim3(kCholThreads), 0, s, p, w, sp, pass, variant); break;
+    case 256: hipLaunchKernelGGL((k_chol<256>), dim3(1), dim3(kCholThreads), 0, s, p, w, sp, pass, variant); break;
+    default: prof_after(s); return hipErrorInvalidValue;
+    }
+    prof_after(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(hipStream_t s, const Problem &, const Work &w, const SchedParams &sp)
+{
+    prof_before(s, "init");
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, w.ctl, sp.info);
+    prof_after(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_out(hipStream_t s, const Work &w, int np, int n, double *G, int64_t ldg)
+{
+    prof_before(s, "gram_out");
+    switch (np) {
+    case 16: hipLaunchKernelGGL((k_gram_out<16>), dim3(4), dim3(256), 0, s, w, n, G, ldg); break;
+    case 32: hipLaunchKernelGGL((k_gram_out<32>), dim3(4), dim3(256), 0, s, w, n, G, ldg); break;
+    case 64: hipLaunchKernelGGL((k_gram_out<64>), dim3(16), dim3(256), 0, s, w, n, G, ldg); break;
+    case 128: hipLaunchKernelGGL((k_gram_out<128>), dim3(64), dim3(256), 0, s, w, n, G, ldg); break;
+    case 256: hipLaunchKernelGGL((k_gram_out<256>), dim3(128), dim3(256), 0, s, w, n, G, ldg); break;
+    default: prof_after(s); return hipErrorInvalidValue;
+    }
+    prof_after(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_factor(hipStream_t s, const Work &w, int np, int n, const double *R, int64_t ldr)
+{
+    prof_before(s, "set_factor");
+    switch (np) {
+    case 16: hipLaunchKernelGGL((k_set_factor<16>), dim3(1), dim3(256), 0, s, w, n, R, ldr); break;
+    case 32: hipLaunchKernelGGL((k_set_factor<32>), dim3(1), dim3(256), 0, s, w, n, R, ldr); break;
+    case 64: hipLaunchKernelGGL((k_set_factor<64>), dim3(1), dim3(256), 0, s, w, n, R, ldr); break;
+    case 128: hipLaunchKernelGGL((k_set_factor<128>), dim3(1), dim3(256), 0, s, w, n, R, ldr); break;
+    case 256: hipLaunchKernelGGL((k_set_factor<256>), dim3(1), dim3(256), 0, s, w, n, R, ldr); break;
+    default: prof_after(s); return hipErrorInvalidValue;
+    }
+    prof_after(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_final_omega(hipStream_t s, const Problem &p, const Work &w, const SchedParams &sp)
+{
+    prof_before(s, "final_omega");
+    switch (p.np) {
+    case 16: hipLaunchKernelGGL((k_final_omega<16>), dim3(1), dim3(256), 0, s, p, w, sp); break;
+    case 32: hipLaunchKernelGGL((k_final_omega<32>), dim3(1), dim3(256), 0, s, p, w, sp); break;
+    case 64: hipLaunchKernelGGL((k_final_omega<64>), dim3(1), dim3(256), 0, s, p, w, sp); break;
+    case 128: hipLaunchKernelGGL((k_final_omega<128>), dim3(1), dim3(256), 0, s, p, w, sp); break;
+    case 256: hipLaunchKernelGGL((k_final_omega<256>), dim3(1), dim3(256), 0, s, p, w, sp); break;
+    default: prof_after(s); return hipErrorInvalidValue;
+    }
+    prof_after(s);
+    return hipGetLastError();
+}
+
+}  // namespace scqr

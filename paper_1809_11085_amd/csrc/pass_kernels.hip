@@ -1,0 +1,543 @@
+// Row-panel kernels of one Cholesky QR pass on gfx950:
+//   * Gram A = X^T X (eq:gram) as a split-m SYRK on FP64 MFMA (16x16x4), upper 16x16 tiles;
+//   * Q = X R~^{-1} by row-wise forward substitution (Algorithm 1 line 4, the row-wise solve
+//     whose backward error equation (eq:backward2) models), fused with the Gram of the new Q
+//     so that a pass reads its input from HBM once and writes Q once;
+//   * the oblique Gram X^T B X for tridiagonal B (Algorithm 4) with one halo row per panel;
+//   * a binary32 MFMA Gram for the FP32-first option;
+//   * a fixed-order reduction of the per-workgroup partial Grams.
+// Every reduction order is fixed, so results are bitwise reproducible run to run.
+#include "scqr_internal.h"
+
+namespace scqr {
+
+// ------------------------------------------------------------------------------------------
+// Control-block predicates.  pass == 0: unconditional; pass < 0: only when the FP32-first
+// pass must be redone in binary64; pass > 0: only when R~ of that pass is ready and the
+// schedule is still active.
+__device__ __forceinline__ bool gate(const Ctl *c, int pass)
+{
+    if (pass == 0) return true;
+    if (pass < 0) return c->active && c->redo_fp64;
+    return c->active && c->pass == pass;
+}
+// The Gram of the Q produced by pass `pass` is needed unless that pass is the last one.
+__device__ __forceinline__ bool gram_needed(const Ctl *c, int pass, int final_gram)
+{
+    if (pass <= 0) return true;
+    return final_gram || c->last != pass;
+}
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ------------------------------------------------------------------------------------------
+// Fused pass for n <= 64.  Each wave owns 64-row panels; lane l holds row l of the panel in
+// registers (one row per lane), so the substitution is plain per-lane FP64 arithmetic with the
+// triangular factor read as wave-uniform (scalar) loads.  The solved rows are staged through a
+// per-wave LDS half-panel (32 rows at a time) into the 16x4 operand layout of the FP64 MFMA,
+// which accumulates all upper 16x16 tiles of Q^T Q in registers.
+//   MODE 0: Gram of X only.  MODE 1: TRSM + Gram.  MODE 2: TRSM only.
+//   F32: Gram in binary32 MFMA, flushed to binary64 after every 64-row chain (MODE 0 only).
+template <int NP, int MODE, bool F32>
+__global__ void __launch_bounds__(256)
+k_pass_small(Problem p, const double *__restrict__ Rt, const double *__restrict__ dinv,
+             double *__restrict__ partials, const Ctl *__restrict__ ctl, int pass, int final_gram)
+{
+    constexpr int NT = NP / 16;
+    constexpr int T = NT * (NT + 1) / 2;
+    constexpr int S = NP + 1;  // LDS row stride (doubles)
+    __shared__ double lds[4 * 32 * S];
+
+    if (!gate(ctl, pass)) return;
+    const bool want_gram = (MODE == 0) || (MODE == 1 && gram_needed(ctl, pass, final_gram));
+
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t W = (int64_t)gridDim.x * 4;
+    const int64_t npanels = (p.m + 63) / 64;
+    const int n = p.n;
+    double *my = lds + wv * 32 * S;
+
+    d4 acc[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] = (d4){0.0, 0.0, 0.0, 0.0};
+
+    for (int64_t pn = (int64_t)blockIdx.x * 4 + wv; pn < npanels; pn += W) {
+        const int64_t row = pn * 64 + lane;
+        const bool live = row < p.m;
+        double t[NP];
+        {
+            const double *xr = p.X + (live ? row : 0) * p.ldx;
+#pragma unroll
+            for (int c = 0; c < NP; ++c) t[c] = (live && c < n) ? xr[c] : 0.0;
+        }
+        if (MODE >= 1) {
+            // Column sweep of the forward substitution q^T R~ = x^T: q_k = t_k / r_kk once
+            // every earlier q has been removed from t_k, then q_k r_kj leaves t_j, j > k.
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                const double qk = t[k] * dinv[k];
+                t[k] = qk;
+#pragma unroll
+                for (int j = k + 1; j < NP; ++j) t[j] = __builtin_fma(-qk, Rt[k * NP + j], t[j]);
+            }
+            if (live) {
+                double *qr = p.Q + row * p.ldq;
+#pragma unroll
+                for (int c = 0; c < NP; ++c)
+                    if (c < n) qr[c] = t[c];
+            }
+        }
+        if (want_gram) {
+            f4 acc32[F32 ? T : 1];
+            if (F32) {
+#pragma unroll
+                for (int u = 0; u < (F32 ? T : 1); ++u) acc32[u] = (f4){0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if ((lane >> 5) == h) {
+                    double *dst = my + (lane & 31) * S;
+#pragma unroll
+                    for (int c = 0; c < NP; ++c) dst[c] = t[c];
+                }
+                wave_sync();
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const double *src = my + (4 * s + (lane >> 4)) * S + (lane & 15);
+                    if (F32) {
+                        float op[NT];
+#pragma unroll
+                        for (int b = 0; b < NT; ++b) op[b] = (float)src[16 * b];
+                        int tt = 0;
+#pragma unroll
+                        for (int I = 0; I < NT; ++I)
+#pragma unroll
+                            for (int J = I; J < NT; ++J, ++tt)
+                                acc32[F32 ? tt : 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                    op[I], op[J], acc32[F32 ? tt : 0], 0, 0, 0);
+                    } else {
+                        double op[NT];
+#pragma unroll
+                        for (int b = 0; b < NT; ++b) op[b] = src[16 * b];
+                        int tt = 0;
+#pragma unroll
+                        for (int I = 0; I < NT; ++I)
+#pragma unroll
+                            for (int J = I; J < NT; ++J, ++tt)
+                                acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[I], op[J],
+                                                                               acc[tt], 0, 0, 0);
+                    }
+                }
+                wave_sync();
+            }
+            if (F32) {
+#pragma unroll
+                for (int u = 0; u < T; ++u)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[u][r] += (double)acc32[F32 ? u : 0][r];
+            }
+        }
+    }
+    if (!want_gram) return;
+
+    // Fixed-order sum of the four waves' tiles: ((w0 + w1) + w2) + w3.
+    __syncthreads();
+    double *red = lds;
+    for (int w = 0; w < 4; ++w) {
+        if (wv == w) {
+#pragma unroll
+            for (int u = 0; u < T; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = u * 256 + r * 64 + lane;
+                    red[e] = (w == 0) ? acc[u][r] : red[e] + acc[u][r];
+                }
+        }
+        __syncthreads();
+    }
+    double *out = partials + (int64_t)blockIdx.x * (T * 256);
+    for (int e = threadIdx.x; e < T * 256; e += 256) out[e] = red[e];
+}
+
+// ------------------------------------------------------------------------------------------
+// Row-wise substitution for n > 64, one row per thread, 64-column blocks: block J starts from
+// x_J, receives -q_k r_kj for every earlier k in increasing order (solved values are re-read
+// from the thread's own output row), then is solved against the diagonal block.
+template <int NP>
+__global__ void __launch_bounds__(256)
+k_trsm_big(Problem p, const double *__restrict__ Rt, const double *__restrict__ dinv,
+           const Ctl *__restrict__ ctl, int pass)
+{
+    if (!gate(ctl, pass)) return;
+    const int n = p.n;
+    for (int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x; row < p.m;
+         row += (int64_t)gridDim.x * 256) {
+        const double *xr = p.X + row * p.ldx;
+        double *qr = p.Q + row * p.ldq;
+        for (int J = 0; J < NP / 64; ++J) {
+            double t[64];
+#pragma unroll
+            for (int c = 0; c < 64; ++c) t[c] = (64 * J + c < n) ? xr[64 * J + c] : 0.0;
+            for (int K = 0; K < J; ++K) {
+                for (int kk = 0; kk < 64; ++kk) {
+                    const int k = 64 * K + kk;
+                    const double qk = (k < n) ? qr[k] : 0.0;
+                    const double *rk = Rt + (int64_t)k * NP + 64 * J;
+#pragma unroll
+                    for (int c = 0; c < 64; ++c) t[c] = __builtin_fma(-qk, rk[c], t[c]);
+                }
+            }
+            const double *rd = Rt + (int64_t)(64 * J) * NP + 64 * J;
+#pragma unroll
+            for (int k = 0; k < 64; ++k) {
+                const double qk = t[k] * dinv[64 * J + k];
+                t[k] = qk;
+#pragma unroll
+                for (int j = k + 1; j < 64; ++j) t[j] = __builtin_fma(-qk, rd[k * NP + j], t[j]);
+            }
+#pragma unroll
+            for (int c = 0; c < 64; ++c)
+                if (64 * J + c < n) qr[64 * J + c] = t[c];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// LDS-staged Gram for any NP (used for n > 64 and for the oblique inner product).  A workgroup
+// of WAVES waves streams 16-row panels through LDS; wave w owns the upper tiles t with
+// t % WAVES == w and accumulates them over every row of the workgroup's share.
+//   OBL: B-Gram X^T (B X) with B tridiagonal; the panel carries one halo row above and below
+//        and (B x)_k = off_{k-1} x_{k-1} + diag_k x_k + off_k x_{k+1} is formed on the fly.
+//   EUC: with OBL, also the Euclidean X^T X (second half of the partial) and the per-workgroup
+//        Gershgorin maximum of B (first-pass shift of equation (eq:finds2B)).
+//   F32: binary32 MFMA, flushed to binary64 after every 64 rows.
+template <int NP, int WAVES, bool OBL, bool EUC, bool F32>
+__global__ void __launch_bounds__(WAVES * 64)
+k_gram_lds(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
+           const Ctl *__restrict__ ctl, int pass, int final_gram)
+{
+    constexpr int NT = NP / 16;
+    constexpr int T = NT * (NT + 1) / 2;
+    constexpr int TPW = (T + WAVES - 1) / WAVES;
+    constexpr int PR = 16;  // rows per panel
+    constexpr int S = NP + 1;
+    constexpr int HALO = OBL ? 1 : 0;
+    __shared__ double xs[(PR + 2 * HALO) * S];
+    __shared__ double cs[OBL ? 3 * (PR) : 1];  // off_{k-1}, diag_k, off_k of the panel rows
+    __shared__ double gmax[WAVES * 64];
+
+    if (!gate(ctl, pass)) return;
+    if (!gram_needed(ctl, pass, final_gram)) return;
+
+    const int nthr = WAVES * 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int n = p.n;
+    const int64_t npanels = (p.m + PR - 1) / PR;
+    // contiguous share of panels per workgroup
+    const int64_t per = (npanels + gridDim.x - 1) / gridDim.x;
+    const int64_t p0 = (int64_t)blockIdx.x * per;
+    const int64_t p1 = (p0 + per < npanels) ? p0 + per : npanels;
+
+    d4 acc[TPW], acce[EUC ? TPW : 1];
+    f4 a32[F32 ? TPW : 1];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) acc[u] = (d4){0.0, 0.0, 0.0, 0.0};
+    if (EUC) {
+#pragma unroll
+        for (int u = 0; u < (EUC ? TPW : 1); ++u) acce[u] = (d4){0.0, 0.0, 0.0, 0.0};
+    }
+    if (F32) {
+#pragma unroll
+        for (int u = 0; u < (F32 ? TPW : 1); ++u) a32[u] = (f4){0.f, 0.f, 0.f, 0.f};
+    }
+    double bm = 0.0;
+    int chain = 0;
+
+    for (int64_t pn = p0; pn < p1; ++pn) {
+        const int64_t r0 = pn * PR;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < (PR + 2 * HALO) * NP; idx += nthr) {
+            const int rr = idx / NP, c = idx % NP;
+            const int64_t row = r0 + rr - HALO;
+            double v = 0.0;
+            if (row >= 0 && row < p.m && c < n) v = p.X[row * p.ldx + c];
+            xs[rr * S + c] = v;
+        }
+        if (OBL) {
+            for (int rr = threadIdx.x; rr < PR; rr += nthr) {
+                const int64_t row = r0 + rr;
+                double lo = 0.0, d = 0.0, up = 0.0;
+                if (row < p.m) {
+                    d = p.bdiag[row];
+                    if (row > 0) lo = p.boff[row - 1];
+                    if (row + 1 < p.m) up = p.boff[row];
+                    if (EUC) {
+                        double g = (row > 0 ? fabs(lo) : 0.0) + fabs(d);
+                        if (row + 1 < p.m) g = g + fabs(up);
+                        bm = g > bm ? g : bm;
+                    }
+                }
+                cs[3 * rr + 0] = lo;
+                cs[3 * rr + 1] = d;
+                cs[3 * rr + 2] = up;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < PR / 4; ++s) {
+            const int rr = 4 * s + (lane >> 4);
+            const double *xrow = xs + (rr + HALO) * S + (lane & 15);
+            double c_lo = 0.0, c_d = 0.0, c_up = 0.0;
+            if (OBL) {
+                c_lo = cs[3 * rr + 0];
+                c_d = cs[3 * rr + 1];
+                c_up = cs[3 * rr + 2];
+            }
+#pragma unroll
+            for (int u = 0; u < TPW; ++u) {
+                const int t = wv + u * WAVES;
+                if (t < T) {
+                    int I, J;
+                    tile_ij(NT, t, I, J);
+                    const double a = xrow[16 * I];
+                    double b = xrow[16 * J];
+                    if (OBL) {
+                        // (B x)_k, evaluated as off_{k-1} x_{k-1} + diag_k x_k, + off_k x_{k+1}
+                        const double bx = c_lo * xrow[16 * J - S] + c_d * b;
+                        const double by = bx + c_up * xrow[16 * J + S];
+                        if (EUC) acce[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acce[u], 0, 0, 0);
+                        b = by;
+                    }
+                    if (F32)
+                        a32[F32 ? u : 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            (float)a, (float)b, a32[F32 ? u : 0], 0, 0, 0);
+                    else
+                        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
+                }
+            }
+        }
+        if (F32) {
+            chain += PR;
+            if (chain >= kF32Chain || pn + 1 == p1) {
+                chain = 0;
+#pragma unroll
+                for (int u = 0; u < TPW; ++u) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[u][r] += (double)a32[F32 ? u : 0][r];
+                    a32[F32 ? u : 0] = (f4){0.f, 0.f, 0.f, 0.f};
+                }
+            }
+        }
+    }
+    const int64_t E = (int64_t)T * 256;
+    double *out = partials + (int64_t)blockIdx.x * (EUC ? 2 * E : E);
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int t = wv + u * WAVES;
+        if (t < T) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                out[t * 256 + r * 64 + lane] = acc[u][r];
+                if (EUC) out[E + t * 256 + r * 64 + lane] = acce[EUC ? u : 0][r];
+            }
+        }
+    }
+    if (EUC) {
+        gmax[threadIdx.x] = bm;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double g = 0.0;
+            for (int i = 0; i < nthr; ++i) g = gmax[i] > g ? gmax[i] : g;
+            bmax[blockIdx.x] = g;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// First level of the fixed-order reduction: lvl2[g][e] = sum over partials p = 32g..32g+31 in
+// increasing p.  The Cholesky kernel adds the level-2 sums in increasing g.
+__global__ void __launch_bounds__(256)
+k_reduce(const double *__restrict__ partials, double *__restrict__ lvl2, int nparts, int64_t elems,
+         const Ctl *__restrict__ ctl, int pass, int final_gram)
+{
+    if (!gate(ctl, pass)) return;
+    if (!gram_needed(ctl, pass, final_gram)) return;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= elems) return;
+    const int g = blockIdx.y;
+    const int p0 = 32 * g, p1 = (p0 + 32 < nparts) ? p0 + 32 : nparts;
+    double s = 0.0;
+    for (int q = p0; q < p1; ++q) s += partials[(int64_t)q * elems + e];
+    lvl2[(int64_t)g * elems + e] = s;
+}
+
+// ------------------------------------------------------------------------------------------
+// Launchers
+static int g_cu_count = 0;
+
+static int cu_count()
+{
+    if (g_cu_count == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            cus > 0)
+            g_cu_count = cus;
+        else
+            g_cu_count = 256;
+    }
+    return g_cu_count;
+}
+
+static bool uses_small(int np, bool oblique) { return np <= 64 && !oblique; }
+
+int pass_grid(int64_t m, int np)
+{
+    const int cus = cu_count();
+    if (np <= 64) {
+        const int64_t panels = (m + 63) / 64;
+        int64_t wg = (panels + 3) / 4;
+        const int64_t cap = 2 * (int64_t)cus;
+        if (wg > cap) wg = cap;
+        return (int)(wg < 1 ? 1 : wg);
+    }
+    const int64_t panels = (m + 15) / 16;
+    int64_t cap = (np <= 128 ? 2 : 1) * (int64_t)cus;
+    int64_t wg = panels < cap ? panels : cap;
+    return (int)(wg < 1 ? 1 : wg);
+}
+
+int64_t pass_partial_elems(int np, bool oblique_first)
+{
+    const int nt = np / 16;
+    const int64_t e = (int64_t)upper_tiles(nt) * 256;
+    return oblique_first ? 2 * e : e;
+}
+
+template <int NP>
+static hipError_t launch_small(hipStream_t s, const Problem &p, const Work &w, int mode, int pass,
+                               bool f32, int final_gram)
+{
+    dim3 grid(w.nwg), block(256);
+    if (mode == 0) {
+        if (f32)
+            hipLaunchKernelGGL((k_pass_small<NP, 0, true>), grid, block, 0, s, p, w.Rt, w.dinv,
+                               w.partials, w.ctl, pass, final_gram);
+        else
+            hipLaunchKernelGGL((k_pass_small<NP, 0, false>), grid, block, 0, s, p, w.Rt, w.dinv,
+                               w.partials, w.ctl, pass, final_gram);
+    } else if (mode == 1) {
+        hipLaunchKernelGGL((k_pass_small<NP, 1, false>), grid, block, 0, s, p, w.Rt, w.dinv,
+                           w.partials, w.ctl, pass, final_gram);
+    } else {
+        hipLaunchKernelGGL((k_pass_small<NP, 2, false>), grid, block, 0, s, p, w.Rt, w.dinv,
+                           w.partials, w.ctl, pass, final_gram);
+    }
+    return hipGetLastError();
+}
+
+template <int NP, int WAVES>
+static hipError_t launch_gram_lds(hipStream_t s, const Problem &p, const Work &w, int pass,
+                                  bool f32, bool obl, bool euc, int final_gram)
+{
+    dim3 grid(w.nwg), block(WAVES * 64);
+    if (obl && euc)
+        hipLaunchKernelGGL((k_gram_lds<NP, WAVES, true, true, false>), grid, block, 0, s, p,
+                           w.partials, w.bmax, w.ctl, pass, final_gram);
+    else if (obl)
+        hipLaunchKernelGGL((k_gram_lds<NP, WAVES, true, false, false>), grid, block, 0, s, p,
+                           w.partials, w.bmax, w.ctl, pass, final_gram);
+    else if (f32)
+        hipLaunchKernelGGL((k_gram_lds<NP, WAVES, false, false, true>), grid, block, 0, s, p,
+                           w.partials, w.bmax, w.ctl, pass, final_gram);
+    else
+        hipLaunchKernelGGL((k_gram_lds<NP, WAVES, false, false, false>), grid, block, 0, s, p,
+                           w.partials, w.bmax, w.ctl, pass, final_gram);
+    return hipGetLastError();
+}
+
+template <int NP>
+static hipError_t launch_trsm_big(hipStream_t s, const Problem &p, const Work &w, int pass)
+{
+    const int cus = cu_count();
+    int64_t blocks = (p.m + 255) / 256;
+    const int64_t cap = 4 * (int64_t)cus;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_trsm_big<NP>), dim3((unsigned)blocks), dim3(256), 0, s, p, w.Rt, w.dinv,
+                       w.ctl, pass);
+    return hipGetLastError();
+}
+
+static hipError_t gram_generic(hipStream_t s, const Problem &p, const Work &w, int pass, bool f32,
+                               bool obl, bool euc, int final_gram)
+{
+    switch (p.np) {
+    case 16: return launch_gram_lds<16, 1>(s, p, w, pass, f32, obl, euc, final_gram);
+    case 32: return launch_gram_lds<32, 4>(s, p, w, pass, f32, obl, euc, final_gram);
+    case 64: return launch_gram_lds<64, 4>(s, p, w, pass, f32, obl, euc, final_gram);
+    case 128: return launch_gram_lds<128, 4>(s, p, w, pass, f32, obl, euc, final_gram);
+    case 256: return launch_gram_lds<256, 8>(s, p, w, pass, f32, obl, euc, final_gram);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pass(hipStream_t s, const Problem &p, const Work &w, int mode, int pass,
+                       bool fp32_gram, bool oblique_gram, bool euclid_too)
+{
+    const int final_gram = (mode & 0x100) ? 1 : 0;
+    mode &= 0xff;
+    hipError_t e = hipSuccess;
+    if (uses_small(p.np, oblique_gram)) {
+        prof_before(s, mode == 0 ? (fp32_gram ? "gram_f32" : "gram") : mode == 1 ? "trsm_gram" : "trsm");
+        switch (p.np) {
+        case 16: e = launch_small<16>(s, p, w, mode, pass, fp32_gram, final_gram); break;
+        case 32: e = launch_small<32>(s, p, w, mode, pass, fp32_gram, final_gram); break;
+        case 64: e = launch_small<64>(s, p, w, mode, pass, fp32_gram, final_gram); break;
+        default: e = hipErrorInvalidValue;
+        }
+        prof_after(s);
+        return e;
+    }
+    // Generic path: separate substitution and Gram kernels.
+    if (mode >= 1) {
+        prof_before(s, "trsm");
+        switch (p.np) {
+        case 16: e = launch_small<16>(s, p, w, 2, pass, false, 0); break;
+        case 32: e = launch_small<32>(s, p, w, 2, pass, false, 0); break;
+        case 64: e = launch_small<64>(s, p, w, 2, pass, false, 0); break;
+        case 128: e = launch_trsm_big<128>(s, p, w, pass); break;
+        case 256: e = launch_trsm_big<256>(s, p, w, pass); break;
+        default: e = hipErrorInvalidValue;
+        }
+        prof_after(s);
+        if (e != hipSuccess) return e;
+    }
+    if (mode <= 1) {
+        Problem pg = p;
+        if (mode == 1) {  // the Gram reads the Q just written
+            pg.X = p.Q;
+            pg.ldx = p.ldq;
+        }
+        prof_before(s, oblique_gram ? (euclid_too ? "gram_b_first" : "gram_b") : (fp32_gram ? "gram_f32" : "gram"));
+        e = gram_generic(s, pg, w, pass, fp32_gram, oblique_gram, euclid_too, final_gram);
+        prof_after(s);
+    }
+    return e;
+}
+
+hipError_t launch_reduce(hipStream_t s, const Work &w, int pass, int64_t elems, int final_gram)
+{
+    dim3 grid((unsigned)((elems + 255) / 256), (unsigned)w.nlvl2), block(256);
+    prof_before(s, "reduce");
+    hipLaunchKernelGGL(k_reduce, grid, block, 0, s, w.partials, w.lvl2, w.nwg, elems, w.ctl, pass,
+                       final_gram);
+    prof_after(s);
+    return hipGetLastError();
+}
+
+}  // namespace scqr

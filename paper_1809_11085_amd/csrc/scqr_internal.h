@@ -1,0 +1,139 @@
+// Internal declarations shared by the translation units of libscqr.so (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "scqr.h"
+
+namespace scqr {
+
+constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53
+constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
+constexpr int kF32Chain = 64;                     // rows per binary32 accumulation chain
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Number of 16 x 16 tiles in the upper triangle of an NP x NP matrix (NP = 16 * NT).
+__host__ __device__ constexpr int upper_tiles(int nt) { return nt * (nt + 1) / 2; }
+
+// Tile t (row-major enumeration of the upper triangle) -> block row I, block column J.
+__host__ __device__ inline void tile_ij(int nt, int t, int &I, int &J)
+{
+    int i = 0, rem = t;
+    while (rem >= nt - i) {
+        rem -= nt - i;
+        ++i;
+    }
+    I = i;
+    J = i + rem;
+}
+
+// Element e of a tile in the FP64 MFMA accumulator layout (lane l, register r; stored at
+// e = r * 64 + l) -> row / column inside the 16 x 16 tile.  The 16x16x4 f64 instruction on
+// gfx950 places D[i][j] in lane j + 16 * (i % 4), register i / 4.
+__host__ __device__ inline void acc64_rc(int e, int &i, int &j)
+{
+    const int r = e >> 6, l = e & 63;
+    i = (l >> 4) + 4 * r;
+    j = l & 15;
+}
+// The 16x16x4 f32 instruction places D[i][j] in lane j + 16 * (i / 4), register i % 4.
+__host__ __device__ inline void acc32_rc(int e, int &i, int &j)
+{
+    const int r = e >> 6, l = e & 63;
+    i = 4 * (l >> 4) + r;
+    j = l & 15;
+}
+
+// Padded width used by the kernels: the smallest of 16, 32, 64, 128, 256 that holds n.
+inline int padded_n(int64_t n)
+{
+    int np = 16;
+    while (np < n) np *= 2;
+    return np;
+}
+
+// Device-side control block of one factorization (lives in the workspace).
+struct Ctl {
+    int32_t active;     // 0 once a breakdown / non-finite Gram stopped the schedule
+    int32_t pass;       // number of passes whose R~ is ready
+    int32_t last;       // pass whose TRSM is the final one (0 = not decided yet)
+    int32_t redo_fp64;  // FP32-first: the first pass must be redone in binary64
+    int32_t status;
+    int32_t f32_pass;   // FP32-first: pass 1 factor came from the binary32 Gram
+    int32_t pad[2];
+    double bnorm;       // ||B||_2 bound (1 for B = I)
+};
+
+// Per-problem description handed to the kernels.
+struct Problem {
+    int64_t m;
+    int32_t n, np;
+    const double *X;
+    int64_t ldx;
+    double *Q;
+    int64_t ldq;
+    double *R;
+    int64_t ldr;
+    const double *bdiag;   // tridiagonal B or nullptr
+    const double *boff;
+};
+
+// Workspace carve-out of one factorization.
+struct Work {
+    Ctl *ctl;
+    double *G;          // np x np reduced Gram (both triangles)
+    double *Ge;         // np x np Euclidean Gram of X for the oblique first-pass shift
+    double *Rt;         // np x np factor of the current pass (identity padding)
+    double *dinv;       // np reciprocals of diag(Rt)
+    double *Racc[2];    // np x np accumulated R (ping-pong)
+    double *partials;   // nwg x parts_elems
+    double *lvl2;       // nlvl2 x parts_elems
+    double *bmax;       // nwg per-workgroup Gershgorin maxima (oblique first pass)
+    int nwg;            // workgroups (= partial count) of the pass kernels
+    int nlvl2;          // level-2 partial count
+    int64_t parts_elems;  // elements of one partial (tiles * 256, doubled for oblique pass 1)
+};
+
+// Schedule parameters copied to the Cholesky kernel by value.
+struct SchedParams {
+    int32_t schedule, shift_mode, precision, max_passes, final_gram, force_bd, zero_shift;
+    int32_t oblique;
+    double custom_alpha;
+    double bnorm_user;
+    double *trace;
+    scqr_info *info;
+};
+
+// ---- launchers (each enqueues on `stream`, returns hipSuccess or the launch error) ----
+int pass_grid(int64_t m, int np);
+int64_t pass_partial_elems(int np, bool oblique_first);
+
+// mode 0: Gram of X only; 1: Q = X R~^{-1} and Gram of Q; 2: Q = X R~^{-1} only.  Bit 0x100
+// of mode asks for the Gram of the final pass too (final_gram option).
+// `pass` selects the predicate on the control block (0 = unconditional, -1 = FP64 redo).
+hipError_t launch_pass(hipStream_t s, const Problem &p, const Work &w, int mode, int pass,
+                       bool fp32_gram, bool oblique_gram, bool euclid_too);
+hipError_t launch_reduce(hipStream_t s, const Work &w, int pass, int64_t elems, int final_gram);
+hipError_t launch_chol(hipStream_t s, const Problem &p, const Work &w, const SchedParams &sp,
+                       int pass, int variant);
+hipError_t launch_init(hipStream_t s, const Problem &p, const Work &w, const SchedParams &sp);
+hipError_t launch_gram_out(hipStream_t s, const Work &w, int np, int n, double *G, int64_t ldg);
+hipError_t launch_set_factor(hipStream_t s, const Work &w, int np, int n, const double *R,
+                             int64_t ldr);
+hipError_t launch_final_omega(hipStream_t s, const Problem &p, const Work &w,
+                              const SchedParams &sp);
+
+// QR adjoint
+hipError_t launch_backward(hipStream_t s, int64_t m, int n, const double *Q, int64_t ldq,
+                           const double *R, int64_t ldr, const double *dQ, int64_t lddq,
+                           const double *dR, int64_t lddr, double *dX, int64_t lddx, void *ws);
+size_t backward_ws_bytes(int64_t m, int n);
+
+// profiling hooks (api.hip)
+void prof_before(hipStream_t s, const char *name);
+void prof_after(hipStream_t s);
+
+}  // namespace scqr

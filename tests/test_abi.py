@@ -1,0 +1,108 @@
+"""The C ABI library loads and exports every symbol that include/scqr.h declares; argument
+errors are returned synchronously (CPU only: no call here reaches a kernel)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "scqr.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_\s\*]*?\b(scqr_[a-z0-9_]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1809_11085_amd as scqr
+    if not os.path.exists(scqr.LIB_PATH):
+        from paper_1809_11085_amd import build
+        build.build()
+    return scqr.lib()
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for must in ["scqr_qr", "scqr_gram", "scqr_trsm", "scqr_qr_batched", "scqr_qr_backward",
+                 "scqr_workspace_bytes", "scqr_status_string", "scqr_default_opts"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings_and_defaults(L):
+    import paper_1809_11085_amd as scqr
+    for s in range(8):
+        assert scqr.status_string(s).startswith("SCQR")
+    o = scqr._Opts()
+    L.scqr_default_opts(ctypes.byref(o))
+    assert o.schedule == 1 and o.shift_mode == 0 and o.max_passes == 6 and o.trace is None
+    assert "gfx950" in scqr.build_info()
+
+
+def test_workspace_bytes_and_invalid_shapes(L):
+    import paper_1809_11085_amd as scqr
+    sz = ctypes.c_size_t()
+    assert L.scqr_workspace_bytes(1 << 22, 64, None, None, ctypes.byref(sz)) == scqr.OK
+    assert sz.value > 64 * 64 * 8
+    assert L.scqr_workspace_bytes(10, 20, None, None, ctypes.byref(sz)) == scqr.E_INVALID
+    assert L.scqr_workspace_bytes(1000, 0, None, None, ctypes.byref(sz)) == scqr.E_INVALID
+    assert L.scqr_workspace_bytes(1000, 257, None, None, ctypes.byref(sz)) == scqr.E_INVALID
+
+
+def test_synchronous_argument_errors(L):
+    import paper_1809_11085_amd as scqr
+    P = 0x100000  # never dereferenced: every call below fails validation first
+    info = ctypes.c_void_p(P)
+    # m < n
+    assert L.scqr_qr(None, 5, 10, P, 10, None, P, 10, P, 10, P, 1 << 30, None, info) == scqr.E_INVALID
+    # n above the maximum
+    assert L.scqr_qr(None, 5000, 300, P, 300, None, P, 300, P, 300, P, 1 << 30, None, info) == scqr.E_UNSUPPORTED
+    # leading dimension too small
+    assert L.scqr_qr(None, 5000, 30, P, 20, None, P, 30, P, 30, P, 1 << 30, None, info) == scqr.E_INVALID
+    # null pointers
+    assert L.scqr_qr(None, 5000, 30, None, 30, None, P, 30, P, 30, P, 1 << 30, None, info) == scqr.E_INVALID
+    # bad option
+    o = scqr._Opts()
+    L.scqr_default_opts(ctypes.byref(o))
+    o.max_passes = 0
+    assert L.scqr_qr(None, 5000, 30, P, 30, None, 0x900000000, 30, 0x800000000, 30, 0x700000000,
+                     1 << 30, ctypes.byref(o), info) == scqr.E_INVALID
+    # workspace too small
+    assert L.scqr_qr(None, 5000, 30, P, 30, None, 0x900000000, 30, 0x800000000, 30, 0x700000000,
+                     16, None, info) == scqr.E_WORKSPACE
+    # R overlapping X
+    assert L.scqr_qr(None, 5000, 30, P, 30, None, 0x900000000, 30, P + 8, 30, 0x700000000,
+                     1 << 30, None, info) == scqr.E_INVALID
+    # FP32-first with an oblique B is outside this build
+    o2 = scqr._Opts()
+    L.scqr_default_opts(ctypes.byref(o2))
+    o2.precision = 1
+    spd = scqr._SpdOp()
+    spd.kind = 1
+    spd.diag = 0x600000000
+    spd.off = 0x610000000
+    assert L.scqr_qr(None, 5000, 30, P, 30, ctypes.byref(spd), 0x900000000, 30, 0x800000000, 30,
+                     0x700000000, 1 << 30, ctypes.byref(o2), info) == scqr.E_UNSUPPORTED
+    # backward: dX aliasing Q
+    assert L.scqr_qr_backward(None, 5000, 30, P, 30, 0x800000000, 30, None, 30, None, 30, P, 30,
+                              0x700000000, 1 << 30) == scqr.E_INVALID
+    # batched: negative batch
+    assert L.scqr_qr_batched(None, -1, None, None, None, None, None, None, 0, None, None) == scqr.E_INVALID
+    assert L.scqr_qr_batched(None, 0, None, None, None, None, None, None, 0, None, None) == scqr.OK
+
+
+def test_product_path_has_no_fallback(monkeypatch, tmp_path):
+    import paper_1809_11085_amd as scqr
+    monkeypatch.setattr(scqr, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(scqr, "_lib", None)
+    with pytest.raises(RuntimeError):
+        scqr.lib()

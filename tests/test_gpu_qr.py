@@ -1,0 +1,193 @@
+"""End-to-end GPU parity of shifted Cholesky QR (Algorithms 2, 3, CholeskyQR2) against the
+oracle, through the C ABI.
+
+* Stepwise replay: the factorization's per-pass trace (input Gram, triangular factor, shift) is
+  checked step by step against the oracle on identical inputs: the Gram against the oracle's
+  Gram of the same iterate, the shift against equation (eq:finds2) on the same Gram, the
+  Cholesky factor against the oracle's Cholesky of the same shifted Gram (and as a backward-
+  stable factorization), the substitution against the oracle's row-wise solve.
+* Invariants of the paper: ||Q^T Q - I||_2 and ||X - QR||_F / ||X||_F <= 1e-13, R upper
+  triangular with positive diagonal.
+* For kappa <= 1e6 the factors themselves match the oracle's: ||R - R_orc||_F / ||R||_F <= 1e-10.
+"""
+import numpy as np
+import pytest
+import torch
+
+import accuracy
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def scqr():
+    import paper_1809_11085_amd as s
+    assert torch.cuda.is_available()
+    s.lib()
+    return s
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def check_chol(G, s, Rg):
+    """Rg is a backward-stable Cholesky factor of G + sI and close to the oracle's factor."""
+    n = G.shape[0]
+    A = G + s * np.eye(n)
+    assert np.all(np.diag(Rg) > 0) and np.all(np.tril(Rg, -1) == 0)
+    g = (n + 1) * U / (1 - (n + 1) * U)
+    assert np.all(np.abs(Rg.T @ Rg - A) <= 4 * g * (np.abs(Rg.T) @ np.abs(Rg)))
+    Ro, bd = oracle.chol_upper(G, s)
+    assert bd == 0
+    w = np.linalg.eigvalsh(A)
+    kap = w[-1] / max(w[0], 1e-300)
+    assert np.linalg.norm(Ro - Rg) <= 10 * n * U * max(kap, 1.0) * np.linalg.norm(Ro)
+
+
+def replay(scqr, X, info, gram_exact=True):
+    """Re-run every pass on the GPU step kernels and compare each step with the oracle."""
+    m, n = X.shape
+    tr = info.trace.cpu().numpy()
+    Qd = dev(X)
+    for p in range(info.passes):
+        Qh = host(Qd)
+        Gg, Rg = tr[p, 0], tr[p, 1]
+        Go = oracle.gram(Qh)
+        gm = m * U / (1 - m * U)
+        assert np.all(np.abs(Gg - Go) <= 2 * gm * (np.abs(Qh).T @ np.abs(Qh)) + 1e-300), f"Gram pass {p + 1}"
+        s = info.shift[p]
+        if info.shifted_mask >> p & 1:
+            lam = np.linalg.eigvalsh(Gg)[-1]
+            assert abs(s - oracle.shift(m, n, lam)) <= 1e-6 * s, f"shift pass {p + 1}"
+        else:
+            assert s == 0.0
+        check_chol(Gg, s, Rg)
+        Qn = scqr.trsm(Qd, dev(Rg))
+        Qnh = host(Qn)
+        Qo = oracle.trsm_rows(Qh, Rg)
+        g = (n + 1) * U / (1 - (n + 1) * U)
+        assert np.all(np.abs(Qnh @ Rg - Qh) <= 3 * g * (np.abs(Qnh) @ np.abs(Rg)) + 1e-300), f"TRSM pass {p + 1}"
+        kr = np.linalg.cond(Rg)
+        assert np.max(np.abs(Qnh - Qo)) <= 10 * n * U * kr * np.max(np.abs(Qo)) + 1e-300
+        Qd = Qn
+    return host(Qd)
+
+
+CASES = [(4096, 32, 1e12), (3000, 10, 1e15), (20000, 64, 1e6), (5000, 17, 1e10), (2000, 100, 1e8),
+         (3000, 128, 1e12), (1500, 256, 1e6), (1000, 1, 1.0), (777, 40, 1e13), (65, 64, 1e4)]
+
+
+@pytest.mark.parametrize("m,n,kappa", CASES)
+def test_stepwise_parity_and_invariants(scqr, m, n, kappa):
+    X = synth.randsvd(m, n, kappa, seed=synth.seed_for(1, m + n))
+    Q, R, info = scqr.qr(dev(X), schedule="adaptive", trace=True)
+    assert info.status == scqr.OK, info
+    Qh, Rh = host(Q), host(R)
+    Qr = replay(scqr, X, info)
+    np.testing.assert_array_equal(Qr, Qh)  # the replay used the same kernels and factors
+    Racc = np.eye(n)
+    for p in range(info.passes):
+        Racc = oracle.trmm_upper(info.trace[p, 1].cpu().numpy(), Racc)
+    assert np.max(np.abs(Racc - Rh)) <= 1e-13 * np.max(np.abs(Rh))
+    om2, _ = accuracy.orthogonality(Qh)
+    assert om2 <= 1e-13
+    assert accuracy.residual(X, Qh, Rh) <= 1e-13
+    assert np.all(np.diag(Rh) > 0) and np.all(np.tril(Rh, -1) == 0)
+    ro = oracle.scqr(X, schedule=oracle.ADAPTIVE)
+    print(f"m={m} n={n} kappa={kappa:.0e}: passes gpu {info.passes} oracle {ro.passes}")
+    if kappa <= 1e6:
+        assert np.linalg.norm(Rh - ro.R) <= 1e-10 * np.linalg.norm(ro.R)
+        assert np.max(np.abs(Qh - ro.Q)) <= 1e-10
+
+
+@pytest.mark.parametrize("schedule,kappa,passes", [("fixed3", 1e12, 3), ("cholqr2", 1e5, 2),
+                                                   ("iterated", 1e5, 2), ("adaptive", 1e5, 3)])
+def test_schedules(scqr, schedule, kappa, passes):
+    X = synth.randsvd(6000, 24, kappa, seed=11)
+    Q, R, info = scqr.qr(dev(X), schedule=schedule)
+    assert info.status == scqr.OK and info.passes == passes
+    sched = {"fixed3": oracle.FIXED3, "cholqr2": oracle.CHOLQR2, "iterated": oracle.ITERATED,
+             "adaptive": oracle.ADAPTIVE}[schedule]
+    ro = oracle.scqr(X, schedule=sched)
+    assert ro.passes == info.passes and ro.shifted_mask == info.shifted_mask
+    assert accuracy.orthogonality(host(Q))[0] <= 1e-13
+    assert accuracy.residual(X, host(Q), host(R)) <= 1e-13
+
+
+@pytest.mark.parametrize("shift", ["fro", "small", "custom"])
+def test_shift_modes(scqr, shift):
+    X = synth.randsvd(5000, 20, 1e9, seed=12)
+    Q, R, info = scqr.qr(dev(X), shift=shift, custom_alpha=1e-12)
+    nrm = info.norm2sq[0]
+    if shift == "fro":
+        assert abs(nrm - np.sum(X * X)) <= 1e-12 * nrm
+        assert abs(info.shift[0] - oracle.shift(5000, 20, nrm)) <= 1e-14 * info.shift[0]
+    elif shift == "small":
+        assert info.shift[0] == U * nrm
+    else:
+        assert info.shift[0] == 1e-12 * nrm
+    if info.status == scqr.OK:
+        assert accuracy.orthogonality(host(Q))[0] <= 1e-13
+
+
+def test_deterministic(scqr):
+    X = dev(synth.randsvd(100000, 64, 1e12, seed=13))
+    Q1, R1, _ = scqr.qr(X)
+    Q2, R2, _ = scqr.qr(X)
+    assert torch.equal(Q1, Q2) and torch.equal(R1, R2)
+
+
+def test_in_place(scqr):
+    X = synth.randsvd(30000, 48, 1e10, seed=14)
+    Xd = dev(X)
+    Q, R, info = scqr.qr(Xd, inplace=True)
+    assert info.status == scqr.OK and Q.data_ptr() == Xd.data_ptr()
+    Qr, Rr, _ = scqr.qr(dev(X))
+    assert torch.equal(Q, Qr) and torch.equal(R, Rr)
+
+
+def test_final_gram_omega(scqr):
+    X = synth.randsvd(50000, 32, 1e11, seed=15)
+    Q, R, info = scqr.qr(dev(X), final_gram=True)
+    assert info.status == scqr.OK
+    _, omf = accuracy.orthogonality(host(Q))
+    assert info.omega_fro <= 1e-13 and abs(info.omega_fro - omf) <= 5e-14
+
+
+def test_forced_breakdown_and_recovery(scqr):
+    X = synth.randsvd(3000, 16, 1e3, seed=16)
+    _, _, info = scqr.qr(dev(X), schedule="fixed3", debug_force_breakdown_pass=2)
+    assert info.status == scqr.E_BREAKDOWN and info.passes == 1 and info.breakdown_mask == 2
+    Q, R, info = scqr.qr(dev(X), schedule="adaptive", debug_force_breakdown_pass=2)
+    assert info.status == scqr.OK and info.breakdown_mask == 2 and info.shifted_mask & 2
+    ro = oracle.scqr(X, schedule=oracle.ADAPTIVE, force_breakdown_pass=2)
+    assert ro.passes == info.passes
+    assert accuracy.orthogonality(host(Q))[0] <= 1e-13
+
+
+def test_zero_and_nonfinite_and_cap(scqr):
+    _, _, info = scqr.qr(torch.zeros((500, 8), dtype=torch.float64, device="cuda"))
+    assert info.status == scqr.E_BREAKDOWN
+    X = synth.randsvd(500, 8, 10.0, seed=17)
+    X[100, 3] = np.nan
+    _, _, info = scqr.qr(dev(X))
+    assert info.status == scqr.E_NONFINITE
+    X = synth.randsvd(3000, 20, 1e15, seed=18)
+    _, _, info = scqr.qr(dev(X), max_passes=2)
+    assert info.status == scqr.E_NOT_CONVERGED and info.passes == 2
+
+
+def test_rank_deficient_reports_status(scqr):
+    X = synth.randsvd(2000, 6, 1e3, seed=19)
+    X[:, 5] = X[:, 2]
+    _, _, info = scqr.qr(dev(X), schedule="fixed3", debug_zero_shift=True)
+    assert info.status == scqr.E_BREAKDOWN
