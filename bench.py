@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Benchmark of shifted Cholesky QR on one MI355X.
+
+Default workload: X = U diag(sigma) V^T with m = 2^22, n = 64, sigma geometric from 1 to 1e-15
+(kappa ~ 1/u), FP64, Euclidean inner product, the ADAPTIVE schedule (Algorithm 3 followed by
+Algorithm 2 continuation) with the paper's shift (eq:finds2).  One step = one complete
+factorization X -> (Q, R) with X resident in HBM.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2|c2b|c1|c3|c5]
+
+The throughput counts the algorithmic flops of the passes actually executed,
+passes * (m n (n+1) + m n^2) (one Gram and one triangular solve per pass).  The roofline
+object reports the dominant kernel's achieved HBM bandwidth from HIP events recorded on the
+launch stream around every kernel of a second, instrumented run of the same K steps; the
+cpu_baseline object times the CPU oracle on the same input on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "shiftedCholQR3 TFLOP/s & % roofline, m=4M n=64 fp64; mixed/batched speedup"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+
+WORKLOADS = {
+    # name: (m, n, kappa, oblique, description)
+    "c2": (1 << 22, 64, 1e15, False, "randsvd m=4194304 n=64 kappa=1e15 fp64, adaptive schedule, paper shift"),
+    "c2b": (1 << 22, 64, 1e6, False, "randsvd m=4194304 n=64 kappa=1e6 fp64, adaptive schedule, paper shift"),
+    "c1": (4096, 32, 1e12, False, "randsvd m=4096 n=32 kappa=1e12 fp64, adaptive schedule, paper shift"),
+    "c3": (1000000, 128, 1e13, True, "randsvd m=1000000 n=128 kappa=1e13, tridiagonal SPD B, fp64"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1809_11085_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str, workload: str, launches_bytes: float):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary of this kernel and
+    workload, scaled by the copy-kernel calibration, or None when missing or stale."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        c = json.load(fh)
+    if c.get("source_hash") != source_hash():
+        return None
+    return c.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(X, passes_gpu, schedule):
+    import oracle
+
+    threads = oracle.num_threads()
+    m, n = X.shape
+    t0 = time.perf_counter()
+    r = oracle.scqr(X, schedule=schedule)
+    dt = time.perf_counter() - t0
+    flops = r.passes * (m * n * (n + 1) + m * n * n)
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"one complete factorization of the same {m}x{n} input ({r.passes} passes, "
+                      f"status {r.status}); {dt:.2f} s wall",
+            "seconds": dt, "passes": r.passes}
+
+
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
+    """Plain device copies of a known size, for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE."""
+    import torch
+
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the method shards over rows with one n x n "
+              "all-reduce per pass, but this build runs and reports a single MI355X (--gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1809_11085_amd as scqr
+    import synth
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if not os.path.exists(scqr.LIB_PATH):
+        from paper_1809_11085_amd import build as hipbuild
+        hipbuild.build()
+    torch.cuda.set_device(0)
+    m, n, kappa, oblique, desc = WORKLOADS[args.workload]
+    cfg_index = {"c1": 0, "c2": 1, "c2b": 1, "c3": 2}[args.workload]
+    t = time.perf_counter()
+    X = synth.randsvd(m, n, kappa, seed=synth.seed_for(cfg_index))
+    B = None
+    if oblique:
+        d, o = synth.tridiag_b(m, seed=synth.seed_for(cfg_index, 1))
+        B = (torch.from_numpy(d).cuda(), torch.from_numpy(o).cuda())
+    Xd = torch.from_numpy(X).cuda()
+    log(f"[bench] generated {args.workload} {m}x{n} kappa={kappa:.0e} in {time.perf_counter() - t:.1f} s")
+
+    plan = scqr.Plan(m, n, "cuda", B=B, schedule="adaptive", shift="paper", max_passes=6)
+    for _ in range(args.warmup):
+        plan.run(Xd)
+    torch.cuda.synchronize()
+    info = plan.read_info()
+    log(f"[bench] warmup done: status={info.status} passes={info.passes} shifts={info.shift}")
+    if info.status != scqr.OK:
+        log(f"[bench] factorization status {scqr.status_string(info.status)}")
+
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.run(Xd)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1) / args.steps
+    info = plan.read_info()
+    p = info.passes
+    flops = p * (m * n * (n + 1) + m * n * n)
+    tflops = flops / (ms * 1e-3) / 1e12
+    log(f"[bench] timed {args.steps} steps: {ms:.3f} ms/step ({wall:.2f} s wall), {tflops:.2f} TFLOP/s")
+
+    # instrumented run of the same steps: per-kernel durations from events on the launch stream
+    scqr.profile_enable(True)
+    for _ in range(args.steps):
+        plan.run(Xd)
+    torch.cuda.synchronize()
+    recs = scqr.profile_read()
+    scqr.profile_enable(False)
+    by = {}
+    for name, dur in recs:
+        by.setdefault(name, []).append(dur)
+    kstats = {}
+    for name, ds in by.items():
+        top = max(ds)
+        active = [d for d in ds if d >= 0.25 * top]
+        kstats[name] = {"launches": len(ds), "active_launches": len(active),
+                        "avg_active_ms": float(np.mean(active)), "total_ms": float(np.sum(ds))}
+    dom = max(kstats, key=lambda k: kstats[k]["total_ms"])
+    avg = kstats[dom]["avg_active_ms"]
+    # algorithmic bytes per launch of the dominant kernel
+    unit_bytes = {"trsm_gram": 16 * m * n, "trsm": 16 * m * n, "gram": 8 * m * n,
+                  "gram_b": 8 * m * n + 16 * m, "gram_b_first": 8 * m * n + 16 * m}.get(dom, 16 * m * n)
+    achieved = unit_bytes / (avg * 1e-3) / 1e9
+    traffic = traffic_from_profiles(dom, args.workload, unit_bytes)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "bytes_per_launch": unit_bytes, "avg_launch_ms": round(avg, 5)}
+    # whole-path roofline: bytes (8 + 16 p) m n at 8 TB/s vs flops at 78.6 TFLOP/s
+    path_bytes = (8 + 16 * p) * m * n
+    t_roof = max(path_bytes / (HBM_PEAK_GBS * 1e9), flops / (FP64_PEAK_TFS * 1e12))
+    result = {
+        "metric": METRIC, "value": round(tflops, 3), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "m": m, "n": n, "kappa": kappa, "passes": p,
+                   "schedule": "adaptive", "shift": "paper"},
+        "roofline": roofline,
+        "path_roofline": {"bytes": path_bytes, "flops": flops, "roofline_ms": round(t_roof * 1e3, 4),
+                          "frac": round(t_roof * 1e3 / ms, 4),
+                          "achieved_GBs": round(path_bytes / (ms * 1e-3) / 1e9, 1)},
+        "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kstats.items()},
+        "status": scqr.status_string(info.status),
+    }
+    if not args.no_accuracy:
+        import accuracy
+
+        t = time.perf_counter()
+        Qh, Rh = plan.Q.cpu().numpy(), plan.R.cpu().numpy()
+        tri = None
+        if oblique:
+            tri = (d, o)
+        om2, omf = accuracy.orthogonality(Qh, tri)
+        res = accuracy.residual(X, Qh, Rh)
+        result["accuracy"] = {"orthogonality_2": om2, "orthogonality_F": omf, "residual": res}
+        log(f"[bench] accuracy: ||Q^TQ-I||_2={om2:.2e} residual={res:.2e} ({time.perf_counter() - t:.1f} s)")
+    if not args.no_cpu_baseline and not oblique:
+        import oracle
+
+        log("[bench] cpu baseline (oracle) ...")
+        cb = cpu_baseline(X, p, oracle.ADAPTIVE)
+        result["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        result["cpu_baseline"]["value"] = round(cb["value"], 5)
+        log(f"[bench] cpu baseline: {cb['value'] * 1e3:.2f} GFLOP/s on {cb['cores']} threads")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

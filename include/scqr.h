@@ -191,8 +191,10 @@ scqr_status scqr_qr_backward(void *stream, int64_t m, int64_t n, const double *Q
  * Kernel timing for measurement.  While enabled, every kernel the library enqueues is
  * bracketed by HIP events recorded on the launch stream (events are created on first use, so
  * keep this off on latency-critical paths).  scqr_profile_read() synchronizes on the
- * recorded events and returns, per kernel name, the number of launches and their summed
- * duration in milliseconds, then clears the record.
+ * recorded events and returns one record per launch, in enqueue order (name and duration in
+ * milliseconds; a launch that its device-side predicate skipped shows a near-zero duration),
+ * then clears the record.  *count receives the number of records available, which may exceed
+ * capacity (only the first `capacity` are copied).
  */
 typedef struct {
     char name[48];

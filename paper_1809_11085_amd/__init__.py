@@ -363,13 +363,12 @@ def profile_enable(on: bool = True) -> None:
     _check(lib().scqr_profile_enable(1 if on else 0), "scqr_profile_enable")
 
 
-def profile_read() -> dict:
-    """{kernel name: (launches, total_ms)} since the last read (synchronizes on the events)."""
-    cap = 64
-    arr = (_KernelStat * cap)()
+def profile_read(capacity: int = 1 << 16) -> list:
+    """[(kernel name, ms)] per launch, in enqueue order, since the last read (synchronizes)."""
+    arr = (_KernelStat * capacity)()
     cnt = ctypes.c_int32()
-    _check(lib().scqr_profile_read(arr, cap, ctypes.byref(cnt)), "scqr_profile_read")
-    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(cnt.value, cap))}
+    _check(lib().scqr_profile_read(arr, capacity, ctypes.byref(cnt)), "scqr_profile_read")
+    return [(arr[i].name.decode(), float(arr[i].total_ms)) for i in range(min(cnt.value, capacity))]
 
 
 def build_info() -> str:

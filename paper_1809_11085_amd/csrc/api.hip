@@ -78,7 +78,7 @@ scqr_status check_opts(const scqr_opts *o)
 struct Layout {
     int np, nwg, nlvl2;
     int64_t elems;
-    size_t off_ctl, off_G, off_Ge, off_Rt, off_dinv, off_R0, off_R1, off_part, off_lvl2, off_bmax, total;
+    size_t off_ctl, off_G, off_Ge, off_Rt, off_dinv, off_R0, off_R1, off_part, off_lvl2, off_gsum, off_cnt, off_bmax, total;
 };
 
 Layout layout(int64_t m, int64_t n, bool oblique)
@@ -97,9 +97,9 @@ Layout layout(int64_t m, int64_t n, bool oblique)
     L.off_Ge = o;
     o += align256(sizeof(double) * np * (np + 1));
     L.off_Rt = o;
-    o += align256(sizeof(double) * np * np);
+    o += align256(sizeof(double) * np * np * SCQR_MAX_PASSES);
     L.off_dinv = o;
-    o += align256(sizeof(double) * np);
+    o += align256(sizeof(double) * np * SCQR_MAX_PASSES);
     L.off_R0 = o;
     o += align256(sizeof(double) * np * np);
     L.off_R1 = o;
@@ -108,6 +108,10 @@ Layout layout(int64_t m, int64_t n, bool oblique)
     o += align256(sizeof(double) * (size_t)L.nwg * (size_t)L.elems);
     L.off_lvl2 = o;
     o += align256(sizeof(double) * (size_t)L.nlvl2 * (size_t)L.elems);
+    L.off_gsum = o;
+    o += align256(sizeof(double) * (size_t)L.elems);
+    L.off_cnt = o;
+    o += align256(sizeof(uint32_t) * (size_t)((L.elems + 255) / 256));
     L.off_bmax = o;
     o += align256(sizeof(double) * (size_t)L.nwg);
     L.total = o;
@@ -121,12 +125,14 @@ Work carve(void *ws, const Layout &L)
     w.ctl = reinterpret_cast<Ctl *>(c + L.off_ctl);
     w.G = reinterpret_cast<double *>(c + L.off_G);
     w.Ge = reinterpret_cast<double *>(c + L.off_Ge);
-    w.Rt = reinterpret_cast<double *>(c + L.off_Rt);
-    w.dinv = reinterpret_cast<double *>(c + L.off_dinv);
+    w.Rhist = reinterpret_cast<double *>(c + L.off_Rt);
+    w.dhist = reinterpret_cast<double *>(c + L.off_dinv);
     w.Racc[0] = reinterpret_cast<double *>(c + L.off_R0);
     w.Racc[1] = reinterpret_cast<double *>(c + L.off_R1);
     w.partials = reinterpret_cast<double *>(c + L.off_part);
     w.lvl2 = reinterpret_cast<double *>(c + L.off_lvl2);
+    w.gsum = reinterpret_cast<double *>(c + L.off_gsum);
+    w.counters = reinterpret_cast<uint32_t *>(c + L.off_cnt);
     w.bmax = reinterpret_cast<double *>(c + L.off_bmax);
     w.nwg = L.nwg;
     w.nlvl2 = L.nlvl2;
@@ -225,7 +231,7 @@ scqr_status scqr_qr(void *stream, int64_t m, int64_t n, const double *X, int64_t
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     Work w = carve(ws, L);
-    Problem p;
+    Problem p{};
     p.m = m;
     p.n = (int)n;
     p.np = L.np;
@@ -276,6 +282,7 @@ scqr_status scqr_qr(void *stream, int64_t m, int64_t n, const double *X, int64_t
         if (e == hipSuccess) e = launch_reduce(s, w, pass, E, fg);
         if (e == hipSuccess && pass < P) e = launch_chol(s, p, w, sp, pass + 1, 0);
     }
+    if (e == hipSuccess) e = launch_finalize_r(s, p, w);
     if (e == hipSuccess && fg) e = launch_final_omega(s, p, w, sp);
     return hip_status(e);
 }
@@ -302,7 +309,9 @@ scqr_status scqr_gram(void *stream, int64_t m, int64_t n, const double *X, int64
     p.bdiag = obl ? B->diag : nullptr;
     p.boff = obl ? B->off : nullptr;
     const int64_t E = pass_partial_elems(L.np, false);
-    hipError_t e = launch_pass(s, p, w, 0, 0, false, obl, false);
+    SchedParams sp{};
+    hipError_t e = launch_init(s, p, w, sp);
+    if (e == hipSuccess) e = launch_pass(s, p, w, 0, 0, false, obl, false);
     if (e == hipSuccess) e = launch_reduce(s, w, 0, E, 0);
     if (e == hipSuccess) e = launch_gram_out(s, w, L.np, (int)n, G, ldg);
     return hip_status(e);
@@ -413,19 +422,14 @@ scqr_status scqr_profile_read(scqr_kernel_stat *stats, int32_t capacity, int32_t
         float ms = 0.f;
         if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
             st = SCQR_E_HIP;
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
-        size_t k = 0;
-        for (; k < agg.size(); ++k)
-            if (r.name == agg[k].name) break;
-        if (k == agg.size()) {
-            scqr_kernel_stat z;
-            std::memset(&z, 0, sizeof(z));
-            std::strncpy(z.name, r.name.c_str(), sizeof(z.name) - 1);
-            agg.push_back(z);
-        }
-        agg[k].launches += 1;
-        agg[k].total_ms += ms;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+        scqr_kernel_stat z;
+        std::memset(&z, 0, sizeof(z));
+        std::strncpy(z.name, r.name.c_str(), sizeof(z.name) - 1);
+        z.launches = 1;
+        z.total_ms = ms;
+        agg.push_back(z);
     }
     const int32_t nout = (int32_t)agg.size() < capacity ? (int32_t)agg.size() : capacity;
     for (int32_t i = 0; i < nout; ++i) stats[i] = agg[i];

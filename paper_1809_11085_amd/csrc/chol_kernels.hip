@@ -32,99 +32,202 @@ __device__ int block_or(int v, double *scratch)
     return s > 0.0;
 }
 
-// Sum of the level-2 partials of tile element e (order g = 0, 1, ...).
-__device__ __forceinline__ double lvl2_sum(const Work &w, int64_t elems, int64_t e)
-{
-    double s = 0.0;
-    for (int g = 0; g < w.nlvl2; ++g) s += w.lvl2[(int64_t)g * elems + e];
-    return s;
-}
-
-// Assemble an np x np symmetric Gram (stride S) from the level-2 partial tiles starting at
-// element offset `base`; the upper triangle is taken and mirrored, entries beyond n are 0.
+// Assemble an np x np symmetric Gram (stride S) from the reduced tiles (gsum, starting at
+// element offset `base`); the upper triangle is taken and mirrored, entries beyond n are 0.
+// Every thread first issues all of its loads (unrolled) so that they overlap.
 template <int NP>
-__device__ void assemble(const Work &w, int n, int64_t elems, int64_t base, bool f32_layout,
-                         double *G, int S)
+__device__ void assemble(const Work &w, int n, int64_t base, bool f32_layout, double *G, int S)
 {
     constexpr int NT = NP / 16;
     constexpr int T = NT * (NT + 1) / 2;
+    constexpr int CH = T < 16 ? T : 16;
     for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) G[(idx / NP) * S + idx % NP] = 0.0;
     __syncthreads();
-    for (int e = threadIdx.x; e < T * 256; e += blockDim.x) {
-        const int t = e >> 8;
-        int I, J, ii, jj;
-        tile_ij(NT, t, I, J);
-        if (f32_layout)
-            acc32_rc(e & 255, ii, jj);
-        else
-            acc64_rc(e & 255, ii, jj);
-        const int i = 16 * I + ii, j = 16 * J + jj;
-        if (i > j || i >= n || j >= n) continue;
-        const double v = lvl2_sum(w, elems, base + e);
-        G[i * S + j] = v;
-        G[j * S + i] = v;
+    for (int u0 = 0; u0 < T; u0 += CH) {
+        double v[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+            if (u0 + u < T) v[u] = w.gsum[base + (u0 + u) * 256 + threadIdx.x];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            if (u0 + u >= T) continue;
+            const int e = (u0 + u) * 256 + threadIdx.x;
+            int I, J, ii, jj;
+            tile_ij(NT, u0 + u, I, J);
+            if (f32_layout)
+                acc32_rc(e & 255, ii, jj);
+            else
+                acc64_rc(e & 255, ii, jj);
+            const int i = 16 * I + ii, j = 16 * J + jj;
+            if (i > j || i >= n || j >= n) continue;
+            G[i * S + j] = v[u];
+            G[j * S + i] = v[u];
+        }
     }
     __syncthreads();
 }
 
-// Rayleigh-quotient power iteration for lambda_max of the symmetric n x n matrix G (stride S):
-// start vector 1/sqrt(n), at most 80 iterations, stop when the quotient changes by <= 1e-9
-// relative.  Run by the whole block; v, y are NP-length scratch arrays.
-template <int NP>
-__device__ double power_lambda(const double *G, int S, int n, double *v, double *y, double *red)
+__device__ __forceinline__ void wave_sync_c()
 {
-    for (int i = threadIdx.x; i < NP; i += blockDim.x) v[i] = (i < n) ? 1.0 / sqrt((double)n) : 0.0;
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Rayleigh-quotient power iteration for lambda_max of the symmetric n x n matrix G (stride S),
+// run by the first wave alone (no workgroup barriers): start vector 1/sqrt(n), at most 100
+// iterations, stop when the quotient changes by <= 1e-6 relative (the stopping rule of the normest
+// estimator the paper names).  The quotient is a lower
+// bound of lambda_max.  Returns the same value in every lane of wave 0.
+template <int NP>
+__device__ double power_lambda_wave(const double *G, int S, int n, double *v)
+{
+    constexpr int C = (NP + 63) / 64;
+    const int lane = threadIdx.x & 63;
+    double vv[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int i = lane + 64 * c;
+        vv[c] = (i < n) ? 1.0 / sqrt((double)n) : 0.0;
+        if (i < NP) v[i] = vv[c];
+    }
+    wave_sync_c();
     double lam = 0.0;
-    for (int it = 0; it < 80; ++it) {
-        double part_vy = 0.0, part_yy = 0.0;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int it = 0; it < 100; ++it) {
+        double y[C], vy = 0.0, yy = 0.0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int i = lane + 64 * c;
             double acc = 0.0;
-            for (int k = 0; k < n; ++k) acc = __builtin_fma(G[i * S + k], v[k], acc);
-            y[i] = acc;
-            part_vy += v[i] * acc;
-            part_yy += acc * acc;
+            if (i < n) {
+                const double *gi = G + i * S;
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int k = 0;
+                for (; k + 4 <= n; k += 4) {
+                    a0 = __builtin_fma(gi[k], v[k], a0);
+                    a1 = __builtin_fma(gi[k + 1], v[k + 1], a1);
+                    a2 = __builtin_fma(gi[k + 2], v[k + 2], a2);
+                    a3 = __builtin_fma(gi[k + 3], v[k + 3], a3);
+                }
+                for (; k < n; ++k) a0 = __builtin_fma(gi[k], v[k], a0);
+                acc = (a0 + a1) + (a2 + a3);
+            }
+            y[c] = acc;
+            vy += vv[c] * acc;
+            yy += acc * acc;
         }
-        const double vy = block_sum(part_vy, red);
-        const double yy = block_sum(part_yy, red);
+        vy = wave_sum(vy);
+        yy = wave_sum(yy);
         const double prev = lam;
         lam = vy;
         if (!(yy > 0.0)) break;
         const double inv = 1.0 / sqrt(yy);
-        for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = y[i] * inv;
-        __syncthreads();
-        if (it > 0 && fabs(lam - prev) <= 1e-9 * fabs(lam)) break;
+        wave_sync_c();
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int i = lane + 64 * c;
+            vv[c] = y[c] * inv;
+            if (i < NP) v[i] = vv[c];
+        }
+        wave_sync_c();
+        if (it > 0 && fabs(lam - prev) <= 1e-6 * fabs(lam)) break;
     }
     return lam;
 }
 
-// In-place upper Cholesky of G + sI (upper triangle of G, stride S).  Returns 0 or 1 + the
-// column whose pivot radicand was <= 0 or not finite.  Right-looking: after step k the trailing
-// entries hold a_ij + s[i==j] - sum_{k' <= k} r_k'i r_k'j, subtracted in increasing k'.
-__device__ int chol_inplace(double *G, int S, int n, double s)
+// Whole-block wrapper: wave 0 iterates, the result is broadcast through LDS.
+template <int NP>
+__device__ double power_lambda(const double *G, int S, int n, double *v, double *red)
 {
-    if (s != 0.0) {
-        for (int i = threadIdx.x; i < n; i += blockDim.x) G[i * S + i] = G[i * S + i] + s;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const double lam = power_lambda_wave<NP>(G, S, n, v);
+        if (threadIdx.x == 0) red[15] = lam;
     }
     __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        const double d = G[k * S + k];
-        if (!(d > 0.0) || !isfinite(d)) return k + 1;
-        const double rkk = sqrt(d);
-        __syncthreads();
-        for (int j = k + threadIdx.x; j < n; j += blockDim.x) G[k * S + j] = (j == k) ? rkk : G[k * S + j] / rkk;
-        __syncthreads();
-        const int rem = n - 1 - k;
-        for (int q = threadIdx.x; q < rem * rem; q += blockDim.x) {
-            // q -> (i, j) over the trailing square; only k < i <= j < n is updated
-            const int a = q / rem, b = q - a * rem;
-            if (a > b) continue;
-            const int ii = k + 1 + a, jj = k + 1 + b;
-            G[ii * S + jj] = __builtin_fma(-G[k * S + ii], G[k * S + jj], G[ii * S + jj]);
+    const double lam = red[15];
+    __syncthreads();
+    return lam;
+}
+
+// In-place upper Cholesky of G + sI (upper triangle of G, stride S), one column per thread
+// (thread l owns column l).  Returns 0 or 1 + the column whose pivot radicand was <= 0 or not
+// finite.  Row j of R is formed from the rows above it (Crout order):
+//   r_jl = ((a_jl - r_0j r_0l) - r_1j r_1l - ...) / r_jj,   l > j,
+// while the pivot radicands d_l = (a_ll + s) - r_0l^2 - r_1l^2 - ... are brought up to date
+// as soon as each r_kl is known (one FMA per column and row), so that r_jj = sqrt(d_j) needs
+// no chain of its own.  Both use the k-ordered subtractions of the textbook algorithm.  The
+// inner dot products only read LDS and are unrolled so that their loads overlap.  With WAVE the
+// first wave alone runs it (n <= 64) and the per-row synchronisation is a wave-level fence.
+template <bool WAVE>
+__device__ int chol_columns(double *G, int S, int n, double s, double *dd)
+{
+    const int l = WAVE ? (threadIdx.x & 63) : threadIdx.x;
+    auto sync = [&]() {
+        if (WAVE)
+            wave_sync_c();
+        else
+            __syncthreads();
+    };
+    if (l < n) dd[l] = G[l * S + l] + s;
+    sync();
+    for (int j = 0; j < n; ++j) {
+        const double d = dd[j];
+        if (!(d > 0.0) || !isfinite(d)) return j + 1;
+        const double rjj = sqrt(d);
+        const bool own = (l > j && l < n);
+        double v = 0.0;
+        if (own) {
+            v = G[j * S + l];
+            const double *cj = G + j;  // cj[k * S] = r_kj
+            const double *cl = G + l;  // cl[k * S] = r_kl
+            int k = 0;
+            for (; k + 8 <= j; k += 8) {
+                double a[8], b[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    a[u] = cj[(k + u) * S];
+                    b[u] = cl[(k + u) * S];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v = __builtin_fma(-a[u], b[u], v);
+            }
+            for (; k < j; ++k) v = __builtin_fma(-cj[k * S], cl[k * S], v);
+            v = v / rjj;
         }
-        __syncthreads();
+        sync();
+        if (own) {
+            G[j * S + l] = v;
+            dd[l] = __builtin_fma(-v, v, dd[l]);
+        }
+        if (l == j) G[j * S + j] = rjj;
+        sync();
     }
     return 0;
+}
+
+template <int NP>
+__device__ int chol_inplace(double *G, int S, int n, double s, double *red, double *dd)
+{
+    if (NP <= 64) {
+        __syncthreads();
+        int bd = 0;
+        if (threadIdx.x < 64) {
+            bd = chol_columns<true>(G, S, n, s, dd);
+            if (threadIdx.x == 0) red[14] = (double)bd;
+        }
+        __syncthreads();
+        bd = (int)red[14];
+        __syncthreads();
+        return bd;
+    }
+    __syncthreads();
+    return chol_columns<false>(G, S, n, s, dd);
 }
 
 __device__ double shift_value(const SchedParams &sp, int64_t m, int n, double norm2sq,
@@ -155,7 +258,6 @@ k_chol(Problem p, Work w, SchedParams sp, int pass, int variant)
     constexpr int S = NP + 1;
     __shared__ double lds[IN_LDS ? NP * S : 1];
     __shared__ double vbuf[NP], ybuf[NP], red[16];
-    __shared__ int sh_flag;
     Ctl *ctl = w.ctl;
     scqr_info *info = sp.info;
 
@@ -169,17 +271,17 @@ k_chol(Problem p, Work w, SchedParams sp, int pass, int variant)
     const bool f32pass = (variant == 0 && pass == 1 && sp.precision == SCQR_PREC_FP32_FIRST);
     const bool obl_first = oblique && pass == 1;
     const int64_t E = (int64_t)upper_tiles(NP / 16) * 256;
-    const int64_t elems = obl_first ? 2 * E : E;
     double *G = IN_LDS ? lds : w.G;
     const int bit = 1 << (pass - 1);
 
-    assemble<NP>(w, n, elems, 0, f32pass, G, S);
+    assemble<NP>(w, n, 0, f32pass, G, S);
 
     // finiteness, ||A - I||_F and trace
     double dev = 0.0, tr = 0.0;
     int bad = 0;
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-        const int i = idx / n, j = idx % n;
+    for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
+        const int i = idx / NP, j = idx % NP;
+        if (i >= n || j >= n) continue;
         const double a = G[i * S + j];
         if (!isfinite(a)) bad = 1;
         const double d = a - (i == j ? 1.0 : 0.0);
@@ -201,23 +303,26 @@ k_chol(Problem p, Work w, SchedParams sp, int pass, int variant)
     if (threadIdx.x == 0) info->gram_dev[pass - 1] = dev;
     if (sp.trace) {
         double *tg = sp.trace + (int64_t)(2 * (pass - 1)) * n * n;
-        for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) tg[idx] = G[(idx / n) * S + idx % n];
+        for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
+            const int i = idx / NP, j = idx % NP;
+            if (i < n && j < n) tg[i * n + j] = G[i * S + j];
+        }
     }
 
     // norm estimate used by a shift of this pass
     auto norm_estimate = [&]() -> double {
         if (obl_first) {
             // ||X||_2 of (eq:finds2B) is the Euclidean norm: Gram X^T X assembled in w.Ge
-            assemble<NP>(w, n, elems, E, false, w.Ge, S);
+            assemble<NP>(w, n, E, false, w.Ge, S);
             if (sp.shift_mode == SCQR_SHIFT_FRO) {
                 double t2 = 0.0;
                 for (int i = threadIdx.x; i < n; i += blockDim.x) t2 += w.Ge[i * S + i];
                 return block_sum(t2, red);
             }
-            return power_lambda<NP>(w.Ge, S, n, vbuf, ybuf, red);
+            return power_lambda<NP>(w.Ge, S, n, vbuf, red);
         }
         if (sp.shift_mode == SCQR_SHIFT_FRO) return tr;
-        return power_lambda<NP>(G, S, n, vbuf, ybuf, red);
+        return power_lambda<NP>(G, S, n, vbuf, red);
     };
     double bfac = 1.0;
     if (obl_first) {
@@ -245,7 +350,7 @@ k_chol(Problem p, Work w, SchedParams sp, int pass, int variant)
         if (f32pass && s > 0.01 * nrm) {
             bd = -1;  // binary32 shift too large: redo the first pass in binary64
         } else {
-            bd = forced ? 1 : chol_inplace(G, S, n, s);
+            bd = forced ? 1 : chol_inplace<NP>(G, S, n, s, red, ybuf);
         }
         if (f32pass && bd != 0) {
             if (threadIdx.x == 0) {
@@ -256,16 +361,16 @@ k_chol(Problem p, Work w, SchedParams sp, int pass, int variant)
         }
         shifted = 1;
     } else {
-        bd = forced ? 1 : chol_inplace(G, S, n, 0.0);
+        bd = forced ? 1 : chol_inplace<NP>(G, S, n, 0.0, red, ybuf);
         if (bd != 0 && (sp.schedule == SCQR_SCHED_ADAPTIVE || sp.schedule == SCQR_SCHED_ITERATED)) {
             if (threadIdx.x == 0) info->breakdown_mask |= bit;
             __syncthreads();
-            assemble<NP>(w, n, elems, 0, false, G, S);
+            assemble<NP>(w, n, 0, false, G, S);
             nrm = norm_estimate();
             s = shift_value(sp, p.m, n, nrm, bfac, oblique, false);
             if (sp.zero_shift) s = 0.0;
             shifted = 1;
-            bd = chol_inplace(G, S, n, s);
+            bd = chol_inplace<NP>(G, S, n, s, red, ybuf);
         }
     }
     if (threadIdx.x == 0) {
@@ -284,7 +389,9 @@ k_chol(Problem p, Work w, SchedParams sp, int pass, int variant)
         return;
     }
 
-    // R~ (identity padding) and reciprocal diagonal for the substitution kernels
+    // R~ of this pass (identity padding) and its reciprocal diagonal, in the pass's slot
+    double *Rslot = w.Rhist + (int64_t)(pass - 1) * NP * NP;
+    double *dslot = w.dhist + (int64_t)(pass - 1) * NP;
     for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
         const int i = idx / NP, j = idx % NP;
         double v;
@@ -292,30 +399,15 @@ k_chol(Problem p, Work w, SchedParams sp, int pass, int variant)
             v = (j >= i) ? G[i * S + j] : 0.0;
         else
             v = (i == j) ? 1.0 : 0.0;
-        w.Rt[idx] = v;
+        Rslot[idx] = v;
     }
-    for (int i = threadIdx.x; i < NP; i += blockDim.x) w.dinv[i] = (i < n) ? 1.0 / G[i * S + i] : 1.0;
+    for (int i = threadIdx.x; i < NP; i += blockDim.x) dslot[i] = (i < n) ? 1.0 / G[i * S + i] : 1.0;
     if (sp.trace) {
         double *tr_ = sp.trace + (int64_t)(2 * (pass - 1) + 1) * n * n;
-        for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-            const int i = idx / n, j = idx % n;
-            tr_[idx] = (j >= i) ? G[i * S + j] : 0.0;
+        for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
+            const int i = idx / NP, j = idx % NP;
+            if (i < n && j < n) tr_[i * n + j] = (j >= i) ? G[i * S + j] : 0.0;
         }
-    }
-    // R := R~ R (upper x upper), ping-pong; pass 1 starts from R = I
-    const double *Rold = w.Racc[(pass + 1) & 1];
-    double *Rnew = w.Racc[pass & 1];
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-        const int i = idx / n, j = idx % n;
-        double v = 0.0;
-        if (j >= i) {
-            if (pass == 1)
-                v = G[i * S + j];
-            else
-                for (int k = i; k <= j; ++k) v = __builtin_fma(G[i * S + k], Rold[k * NP + j], v);
-        }
-        Rnew[i * NP + j] = v;
-        p.R[(int64_t)i * p.ldr + j] = v;
     }
 
     if (threadIdx.x == 0) {
@@ -344,8 +436,9 @@ k_chol(Problem p, Work w, SchedParams sp, int pass, int variant)
 }
 
 // Initialise the control block and the caller's info record.
-__global__ void k_init(Ctl *ctl, scqr_info *info)
+__global__ void k_init(Ctl *ctl, scqr_info *info, uint32_t *counters, int ncounters)
 {
+    for (int i = threadIdx.x; i < ncounters; i += blockDim.x) counters[i] = 0u;
     if (threadIdx.x == 0) {
         ctl->active = 1;
         ctl->pass = 0;
@@ -379,7 +472,7 @@ __global__ void __launch_bounds__(256) k_gram_out(Work w, int n, double *G, int6
         acc64_rc((int)(e & 255), ii, jj);
         const int i = 16 * I + ii, j = 16 * J + jj;
         if (i > j || i >= n || j >= n) continue;
-        const double v = lvl2_sum(w, E, e);
+        const double v = w.gsum[e];
         G[(int64_t)i * ldg + j] = v;
         G[(int64_t)j * ldg + i] = v;
     }
@@ -396,9 +489,82 @@ __global__ void __launch_bounds__(256) k_set_factor(Work w, int n, const double 
             v = (j >= i) ? R[(int64_t)i * ldr + j] : 0.0;
         else
             v = (i == j) ? 1.0 : 0.0;
-        w.Rt[idx] = v;
+        w.Rhist[idx] = v;
     }
-    for (int i = threadIdx.x; i < NP; i += blockDim.x) w.dinv[i] = (i < n) ? 1.0 / R[(int64_t)i * ldr + i] : 1.0;
+    for (int i = threadIdx.x; i < NP; i += blockDim.x) w.dhist[i] = (i < n) ? 1.0 / R[(int64_t)i * ldr + i] : 1.0;
+}
+
+// R = R~_p ... R~_2 R~_1 over the passes that were applied (R := R~ R of Algorithms 2 and 3),
+// written to the caller's R with a zero lower triangle; the identity if no pass was applied.
+// One workgroup; the running product stays in LDS when it fits, each entry of a product is a
+// sum over k = i..j taken in four interleaved partial sums.
+template <int NP>
+__global__ void __launch_bounds__(256) k_finalize_r(Problem p, Work w)
+{
+    constexpr bool IN_LDS = NP <= 128;
+    constexpr int S = NP + 1;
+    constexpr int VALS = IN_LDS ? NP * NP / 256 : 1;
+    __shared__ double acc_l[IN_LDS ? NP * S : 1];
+    __shared__ double fl[NP <= 64 ? NP * NP : 1];
+    const int n = p.n;
+    const int passes = w.ctl->pass;
+    double *A = IN_LDS ? acc_l : w.Racc[0];
+    const int sa = IN_LDS ? S : NP;
+#pragma unroll 16
+    for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
+        const int i = idx / NP, j = idx % NP;
+        A[i * sa + j] = (passes >= 1) ? w.Rhist[idx] : (i == j ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int q = 2; q <= passes; ++q) {
+        const double *F = w.Rhist + (int64_t)(q - 1) * NP * NP;
+        if (NP <= 64) {  // stage the factor in LDS next to the running product
+#pragma unroll 16
+            for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) fl[idx] = F[idx];
+            __syncthreads();
+            F = fl;
+        }
+        double *D = IN_LDS ? nullptr : w.Racc[(q & 1) ? 0 : 1];  // global ping-pong target
+        const double *Asrc = A;
+        double vals[VALS];
+        int cnt = 0;
+        for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x, ++cnt) {
+            const int i = idx / NP, j = idx % NP;
+            double v = 0.0;
+            if (j >= i && i < n && j < n) {
+                // new[i][j] = sum_{k=i..j} F[i][k] A[k][j], four interleaved partial sums
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int k = i;
+                for (; k + 4 <= j + 1; k += 4) {
+                    a0 = __builtin_fma(F[i * NP + k], Asrc[k * sa + j], a0);
+                    a1 = __builtin_fma(F[i * NP + k + 1], Asrc[(k + 1) * sa + j], a1);
+                    a2 = __builtin_fma(F[i * NP + k + 2], Asrc[(k + 2) * sa + j], a2);
+                    a3 = __builtin_fma(F[i * NP + k + 3], Asrc[(k + 3) * sa + j], a3);
+                }
+                for (; k <= j; ++k) a0 = __builtin_fma(F[i * NP + k], Asrc[k * sa + j], a0);
+                v = (a0 + a1) + (a2 + a3);
+            } else if (i >= n || j >= n) {
+                v = (i == j) ? 1.0 : 0.0;
+            }
+            if (IN_LDS)
+                vals[cnt < VALS ? cnt : 0] = v;
+            else
+                D[idx] = v;
+        }
+        __syncthreads();
+        if (IN_LDS) {
+            cnt = 0;
+            for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x, ++cnt)
+                A[(idx / NP) * sa + idx % NP] = vals[cnt < VALS ? cnt : 0];
+        } else {
+            A = D;
+        }
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
+        const int i = idx / NP, j = idx % NP;
+        if (i < n && j < n) p.R[(int64_t)i * p.ldr + j] = (j >= i) ? A[i * sa + j] : 0.0;
+    }
 }
 
 // ||G - I||_F of the final Gram (final_gram option).
@@ -419,7 +585,7 @@ __global__ void __launch_bounds__(256) k_final_omega(Problem p, Work w, SchedPar
         acc64_rc(e & 255, ii, jj);
         const int i = 16 * I + ii, j = 16 * J + jj;
         if (i > j || i >= n || j >= n) continue;
-        const double d = lvl2_sum(w, E, e) - (i == j ? 1.0 : 0.0);
+        const double d = w.gsum[e] - (i == j ? 1.0 : 0.0);
         acc += (i == j ? 1.0 : 2.0) * d * d;
     }
     acc = block_sum(acc, red);
@@ -446,7 +612,8 @@ hipError_t launch_chol(hipStream_t s, const Problem &p, const Work &w, const Sch
 hipError_t launch_init(hipStream_t s, const Problem &, const Work &w, const SchedParams &sp)
 {
     prof_before(s, "init");
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, w.ctl, sp.info);
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, w.ctl, sp.info, w.counters,
+                       (int)((w.parts_elems + 255) / 256));
     prof_after(s);
     return hipGetLastError();
 }
@@ -475,6 +642,21 @@ hipError_t launch_set_factor(hipStream_t s, const Work &w, int np, int n, const 
     case 64: hipLaunchKernelGGL((k_set_factor<64>), dim3(1), dim3(256), 0, s, w, n, R, ldr); break;
     case 128: hipLaunchKernelGGL((k_set_factor<128>), dim3(1), dim3(256), 0, s, w, n, R, ldr); break;
     case 256: hipLaunchKernelGGL((k_set_factor<256>), dim3(1), dim3(256), 0, s, w, n, R, ldr); break;
+    default: prof_after(s); return hipErrorInvalidValue;
+    }
+    prof_after(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_r(hipStream_t s, const Problem &p, const Work &w)
+{
+    prof_before(s, "finalize_r");
+    switch (p.np) {
+    case 16: hipLaunchKernelGGL((k_finalize_r<16>), dim3(1), dim3(256), 0, s, p, w); break;
+    case 32: hipLaunchKernelGGL((k_finalize_r<32>), dim3(1), dim3(256), 0, s, p, w); break;
+    case 64: hipLaunchKernelGGL((k_finalize_r<64>), dim3(1), dim3(256), 0, s, p, w); break;
+    case 128: hipLaunchKernelGGL((k_finalize_r<128>), dim3(1), dim3(256), 0, s, p, w); break;
+    case 256: hipLaunchKernelGGL((k_finalize_r<256>), dim3(1), dim3(256), 0, s, p, w); break;
     default: prof_after(s); return hipErrorInvalidValue;
     }
     prof_after(s);

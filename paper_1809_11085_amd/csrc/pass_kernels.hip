@@ -35,62 +35,182 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // ------------------------------------------------------------------------------------------
-// Fused pass for n <= 64.  Each wave owns 64-row panels; lane l holds row l of the panel in
-// registers (one row per lane), so the substitution is plain per-lane FP64 arithmetic with the
-// triangular factor read as wave-uniform (scalar) loads.  The solved rows are staged through a
-// per-wave LDS half-panel (32 rows at a time) into the 16x4 operand layout of the FP64 MFMA,
-// which accumulates all upper 16x16 tiles of Q^T Q in registers.
+// Fused pass for n <= 64.  Each wave owns panels of PR rows staged in a per-wave LDS buffer
+// (coalesced 16-byte global loads and stores).  Q = X R~^{-1} is a blocked row-wise
+// substitution over 16-column blocks J:
+//   T_J = X_J - sum_{K<J} Q_K R~_KJ   on FP64 MFMA, with -R~_KJ held in registers for the whole
+//                                     kernel in the 4x16 B-operand layout;
+//   Q_J = T_J R~_JJ^{-1}              one row per lane, forward substitution against the 16x16
+//                                     diagonal block (wave-uniform scalar loads), multiplying by
+//                                     the reciprocal diagonal.
+// Each q_ij is thus x_ij minus the products q_ik r_kj, k < j, divided by r_jj: a row-wise
+// substitution in blocked order, whose backward error is bounded row by row as in (eq:backward2).
+// The solved panel then feeds the FP64 MFMA Gram (all upper 16x16 tiles in registers).
 //   MODE 0: Gram of X only.  MODE 1: TRSM + Gram.  MODE 2: TRSM only.
 //   F32: Gram in binary32 MFMA, flushed to binary64 after every 64-row chain (MODE 0 only).
-template <int NP, int MODE, bool F32>
-__global__ void __launch_bounds__(256)
-k_pass_small(Problem p, const double *__restrict__ Rt, const double *__restrict__ dinv,
-             double *__restrict__ partials, const Ctl *__restrict__ ctl, int pass, int final_gram)
+//   VEC: n even, even leading dimensions and 16-byte aligned X, Q (pairs of doubles per access).
+//   PR: rows per panel (32: 8 waves per workgroup, 64: 4 waves).
+template <int NP, int MODE, bool F32, bool VEC, int PR>
+__global__ void __launch_bounds__(PR == 64 ? 256 : 512)
+k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
+            const double *__restrict__ dinv, double *__restrict__ partials,
+            const Ctl *__restrict__ ctl, int pass, int final_gram)
 {
+    // Qout == p.Q; passing it as a restrict parameter lets the factor loads stay scalar.  When
+    // Q aliases X every row is read before it is written by the same wave.
+    constexpr int WAVES = PR == 64 ? 4 : 8;
     constexpr int NT = NP / 16;
     constexpr int T = NT * (NT + 1) / 2;
-    constexpr int S = NP + 1;  // LDS row stride (doubles)
-    __shared__ double lds[4 * 32 * S];
+    constexpr int NOFF = NT * (NT - 1) / 2;
+    constexpr int S = NP + 2;  // LDS row stride (doubles): 2*S = 4 mod 32 dwords
+    constexpr int PANEL = PR * S;
+    constexpr int LDSZ = (WAVES * PANEL > T * 256) ? WAVES * PANEL : T * 256;
+    constexpr int PP = PR * NP / 2 / 64;  // double pairs per lane per panel
+    static_assert((PR * NP / 2) % 64 == 0, "panel must split evenly over a wave");
+    constexpr int BL = (MODE >= 1 && NOFF > 0) ? NOFF * 4 * 64 : 1;
+    __shared__ __attribute__((aligned(16))) double lds[LDSZ];
+    __shared__ double bl[BL];
 
     if (!gate(ctl, pass)) return;
     const bool want_gram = (MODE == 0) || (MODE == 1 && gram_needed(ctl, pass, final_gram));
 
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t W = (int64_t)gridDim.x * 4;
-    const int64_t npanels = (p.m + 63) / 64;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t W = (int64_t)gridDim.x * WAVES;
+    const int64_t npanels = (p.m + PR - 1) / PR;
     const int n = p.n;
-    double *my = lds + wv * 32 * S;
+    double *P = lds + wv * PANEL;
+    const int li = lane & 15, lk = lane >> 4;
+
+    // -R~_KJ (K < J) in the B-operand layout, one 64-entry vector per (block pair, k-step):
+    // entry l holds -r[16K + 4s + l/16][16J + l%16].
+    if (MODE >= 1 && NOFF > 0) {
+        for (int idx = threadIdx.x; idx < NOFF * 4 * 64; idx += WAVES * 64) {
+            const int l = idx & 63, s4 = (idx >> 6) & 3, pi = idx >> 8;
+            int J = 1, K = pi;
+            while (K >= J) {
+                K -= J;
+                ++J;
+            }
+            bl[idx] = -Rt[(16 * K + 4 * s4 + (l >> 4)) * NP + 16 * J + (l & 15)];
+        }
+        __syncthreads();
+    }
 
     d4 acc[T];
 #pragma unroll
-    for (int t = 0; t < T; ++t) acc[t] = (d4){0.0, 0.0, 0.0, 0.0};
+    for (int u = 0; u < T; ++u) acc[u] = (d4){0.0, 0.0, 0.0, 0.0};
 
-    for (int64_t pn = (int64_t)blockIdx.x * 4 + wv; pn < npanels; pn += W) {
-        const int64_t row = pn * 64 + lane;
-        const bool live = row < p.m;
-        double t[NP];
-        {
-            const double *xr = p.X + (live ? row : 0) * p.ldx;
+    // X panel pn -> registers (pairs of doubles, coalesced); issued one panel ahead so that the
+    // loads of the next panel overlap the MFMA work of the current one.
+    double2 pre[PP];
+    auto load_panel = [&](int64_t pnl) {
+        const int64_t rb = pnl * PR;
 #pragma unroll
-            for (int c = 0; c < NP; ++c) t[c] = (live && c < n) ? xr[c] : 0.0;
+        for (int i = 0; i < PP; ++i) {
+            const int e2 = lane + 64 * i;
+            const int r = e2 / (NP / 2), c = 2 * (e2 % (NP / 2));
+            const int64_t row = rb + r;
+            double a = 0.0, b = 0.0;
+            if (row < p.m) {
+                const double *src = p.X + row * p.ldx + c;
+                if (VEC) {
+                    if (c < n) {
+                        const double2 v = *reinterpret_cast<const double2 *>(src);
+                        a = v.x;
+                        b = v.y;
+                    }
+                } else {
+                    if (c < n) a = src[0];
+                    if (c + 1 < n) b = src[1];
+                }
+            }
+            pre[i] = make_double2(a, b);
         }
+    };
+    int64_t pn = (int64_t)blockIdx.x * WAVES + wv;
+    if (pn < npanels) load_panel(pn);
+    for (; pn < npanels; pn += W) {
+        const int64_t r0 = pn * PR;
+        const int64_t nxt = pn + W;
+        // ---- staged X panel -> LDS
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int e2 = lane + 64 * i;
+            const int r = e2 / (NP / 2), c = 2 * (e2 % (NP / 2));
+            *reinterpret_cast<double2 *>(P + r * S + c) = pre[i];
+        }
+        wave_sync();
         if (MODE >= 1) {
-            // Column sweep of the forward substitution q^T R~ = x^T: q_k = t_k / r_kk once
-            // every earlier q has been removed from t_k, then q_k r_kj leaves t_j, j > k.
+            // The opaque zero keeps the diagonal-block loads inside the panel loop (as scalar
+            // loads of a 4 KB working set) instead of hoisting them into spilled registers.
+            const int64_t off = pn & (int64_t)p.zero;
+            int pi0 = 0;
 #pragma unroll
-            for (int k = 0; k < NP; ++k) {
-                const double qk = t[k] * dinv[k];
-                t[k] = qk;
+            for (int J = 0; J < NT; ++J) {
+                if (J > 0) {
 #pragma unroll
-                for (int j = k + 1; j < NP; ++j) t[j] = __builtin_fma(-qk, Rt[k * NP + j], t[j]);
+                    for (int g = 0; g < PR / 16; ++g) {
+                        double *blk = P + (16 * g + lk) * S + 16 * J + li;
+                        d4 d;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) d[r] = blk[4 * r * S];
+                        const double *arow = P + (16 * g + li) * S + lk;
+                        int pi = pi0;
+#pragma unroll
+                        for (int K = 0; K < J; ++K, ++pi)
+#pragma unroll
+                            for (int s4 = 0; s4 < 4; ++s4)
+                                d = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * K + 4 * s4],
+                                                                         bl[(pi * 4 + s4) * 64 + lane], d, 0, 0, 0);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) blk[4 * r * S] = d[r];
+                    }
+                    pi0 += J;
+                    wave_sync();
+                }
+                if (lane < PR) {
+                    double *mr = P + lane * S + 16 * J;
+                    double t[16];
+#pragma unroll
+                    for (int c = 0; c < 16; c += 2) {
+                        const double2 v = *reinterpret_cast<const double2 *>(mr + c);
+                        t[c] = v.x;
+                        t[c + 1] = v.y;
+                    }
+                    const double *Rd = Rt + off + (16 * J) * NP + 16 * J;
+                    const double *dd = dinv + off + 16 * J;
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        const double qk = t[k] * dd[k];
+                        t[k] = qk;
+#pragma unroll
+                        for (int j = k + 1; j < 16; ++j) t[j] = __builtin_fma(-qk, Rd[k * NP + j], t[j]);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 16; c += 2) *reinterpret_cast<double2 *>(mr + c) = make_double2(t[c], t[c + 1]);
+                }
+                wave_sync();
             }
-            if (live) {
-                double *qr = p.Q + row * p.ldq;
+            // ---- Q panel -> HBM
 #pragma unroll
-                for (int c = 0; c < NP; ++c)
-                    if (c < n) qr[c] = t[c];
+            for (int i = 0; i < PP; ++i) {
+                const int e2 = lane + 64 * i;
+                const int r = e2 / (NP / 2), c = 2 * (e2 % (NP / 2));
+                const int64_t row = r0 + r;
+                if (row < p.m && c < n) {
+                    const double2 v = *reinterpret_cast<const double2 *>(P + r * S + c);
+                    double *dst = Qout + row * p.ldq + c;
+                    if (VEC) {
+                        *reinterpret_cast<double2 *>(dst) = v;
+                    } else {
+                        dst[0] = v.x;
+                        if (c + 1 < n) dst[1] = v.y;
+                    }
+                }
             }
         }
+        if (nxt < npanels) load_panel(nxt);
         if (want_gram) {
             f4 acc32[F32 ? T : 1];
             if (F32) {
@@ -98,41 +218,29 @@ k_pass_small(Problem p, const double *__restrict__ Rt, const double *__restrict_
                 for (int u = 0; u < (F32 ? T : 1); ++u) acc32[u] = (f4){0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if ((lane >> 5) == h) {
-                    double *dst = my + (lane & 31) * S;
+            for (int s = 0; s < PR / 4; ++s) {
+                const double *src = P + (4 * s + lk) * S + li;
+                if (F32) {
+                    float op[NT];
 #pragma unroll
-                    for (int c = 0; c < NP; ++c) dst[c] = t[c];
+                    for (int b = 0; b < NT; ++b) op[b] = (float)src[16 * b];
+                    int tt = 0;
+#pragma unroll
+                    for (int I = 0; I < NT; ++I)
+#pragma unroll
+                        for (int J = I; J < NT; ++J, ++tt)
+                            acc32[F32 ? tt : 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(op[I], op[J], acc32[F32 ? tt : 0], 0, 0, 0);
+                } else {
+                    double op[NT];
+#pragma unroll
+                    for (int b = 0; b < NT; ++b) op[b] = src[16 * b];
+                    int tt = 0;
+#pragma unroll
+                    for (int I = 0; I < NT; ++I)
+#pragma unroll
+                        for (int J = I; J < NT; ++J, ++tt)
+                            acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[I], op[J], acc[tt], 0, 0, 0);
                 }
-                wave_sync();
-#pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    const double *src = my + (4 * s + (lane >> 4)) * S + (lane & 15);
-                    if (F32) {
-                        float op[NT];
-#pragma unroll
-                        for (int b = 0; b < NT; ++b) op[b] = (float)src[16 * b];
-                        int tt = 0;
-#pragma unroll
-                        for (int I = 0; I < NT; ++I)
-#pragma unroll
-                            for (int J = I; J < NT; ++J, ++tt)
-                                acc32[F32 ? tt : 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                                    op[I], op[J], acc32[F32 ? tt : 0], 0, 0, 0);
-                    } else {
-                        double op[NT];
-#pragma unroll
-                        for (int b = 0; b < NT; ++b) op[b] = src[16 * b];
-                        int tt = 0;
-#pragma unroll
-                        for (int I = 0; I < NT; ++I)
-#pragma unroll
-                            for (int J = I; J < NT; ++J, ++tt)
-                                acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[I], op[J],
-                                                                               acc[tt], 0, 0, 0);
-                    }
-                }
-                wave_sync();
             }
             if (F32) {
 #pragma unroll
@@ -141,13 +249,14 @@ k_pass_small(Problem p, const double *__restrict__ Rt, const double *__restrict_
                     for (int r = 0; r < 4; ++r) acc[u][r] += (double)acc32[F32 ? u : 0][r];
             }
         }
+        wave_sync();
     }
     if (!want_gram) return;
 
-    // Fixed-order sum of the four waves' tiles: ((w0 + w1) + w2) + w3.
+    // Fixed-order sum of the waves' tiles: (((w0 + w1) + w2) + ...).
     __syncthreads();
     double *red = lds;
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < WAVES; ++w) {
         if (wv == w) {
 #pragma unroll
             for (int u = 0; u < T; ++u)
@@ -160,7 +269,7 @@ k_pass_small(Problem p, const double *__restrict__ Rt, const double *__restrict_
         __syncthreads();
     }
     double *out = partials + (int64_t)blockIdx.x * (T * 256);
-    for (int e = threadIdx.x; e < T * 256; e += 256) out[e] = red[e];
+    for (int e = threadIdx.x; e < T * 256; e += WAVES * 64) out[e] = red[e];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -358,21 +467,52 @@ k_gram_lds(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
 }
 
 // ------------------------------------------------------------------------------------------
-// First level of the fixed-order reduction: lvl2[g][e] = sum over partials p = 32g..32g+31 in
-// increasing p.  The Cholesky kernel adds the level-2 sums in increasing g.
+// Fixed-order reduction of the per-workgroup partial Grams.  Block (x, g) adds partials
+// p = 32g .. 32g+31 in increasing p for its 256 elements; the last of the blocks of column x
+// to finish (arrival counter after a device-scope fence) adds those level-2 sums in increasing
+// g and writes the reduced tiles.  The result does not depend on which block arrives last.
 __global__ void __launch_bounds__(256)
-k_reduce(const double *__restrict__ partials, double *__restrict__ lvl2, int nparts, int64_t elems,
+k_reduce(const double *__restrict__ partials, double *__restrict__ lvl2, double *__restrict__ gsum,
+         uint32_t *__restrict__ counters, int nparts, int nlvl2, int64_t elems,
          const Ctl *__restrict__ ctl, int pass, int final_gram)
 {
+    __shared__ int last;
     if (!gate(ctl, pass)) return;
     if (!gram_needed(ctl, pass, final_gram)) return;
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= elems) return;
+    const bool live = e < elems;
     const int g = blockIdx.y;
     const int p0 = 32 * g, p1 = (p0 + 32 < nparts) ? p0 + 32 : nparts;
-    double s = 0.0;
-    for (int q = p0; q < p1; ++q) s += partials[(int64_t)q * elems + e];
-    lvl2[(int64_t)g * elems + e] = s;
+    if (live) {
+        double v[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) v[q] = (p0 + q < p1) ? partials[(int64_t)(p0 + q) * elems + e] : 0.0;
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < 32; ++q)
+            if (p0 + q < p1) s += v[q];
+        lvl2[(int64_t)g * elems + e] = s;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = (atomicAdd(&counters[blockIdx.x], 1u) == (uint32_t)(nlvl2 - 1));
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (live) {
+        double s = 0.0;
+        int q = 0;
+        for (; q + 8 <= nlvl2; q += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = lvl2[(int64_t)(q + u) * elems + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; q < nlvl2; ++q) s += lvl2[(int64_t)q * elems + e];
+        gsum[e] = s;
+    }
+    if (threadIdx.x == 0) counters[blockIdx.x] = 0u;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -399,9 +539,10 @@ int pass_grid(int64_t m, int np)
 {
     const int cus = cu_count();
     if (np <= 64) {
-        const int64_t panels = (m + 63) / 64;
-        int64_t wg = (panels + 3) / 4;
-        const int64_t cap = 2 * (int64_t)cus;
+        // one workgroup of 8 waves (32-row panels) per CU, persistent over the panels
+        const int64_t panels = (m + 31) / 32;
+        int64_t wg = (panels + 7) / 8;
+        const int64_t cap = (int64_t)cus;
         if (wg > cap) wg = cap;
         return (int)(wg < 1 ? 1 : wg);
     }
@@ -418,25 +559,41 @@ int64_t pass_partial_elems(int np, bool oblique_first)
     return oblique_first ? 2 * e : e;
 }
 
+// Rows per panel of the fused kernel (64: 4 waves per workgroup, 32: 8 waves).
+constexpr int kPanelRows = 32;
+
+template <int NP, bool VEC>
+static void launch_small_v(hipStream_t s, const Problem &p, const Work &w, int mode, int pass,
+                           bool f32, int final_gram)
+{
+    constexpr int PR = kPanelRows;
+    dim3 grid(w.nwg), block(PR == 64 ? 256 : 512);
+    if (mode == 0) {
+        if (f32)
+            hipLaunchKernelGGL((k_pass_tile<NP, 0, true, VEC, PR>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
+                               w.partials, w.ctl, pass, final_gram);
+        else
+            hipLaunchKernelGGL((k_pass_tile<NP, 0, false, VEC, PR>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
+                               w.partials, w.ctl, pass, final_gram);
+    } else if (mode == 1) {
+        hipLaunchKernelGGL((k_pass_tile<NP, 1, false, VEC, PR>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
+                           w.partials, w.ctl, pass, final_gram);
+    } else {
+        hipLaunchKernelGGL((k_pass_tile<NP, 2, false, VEC, PR>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
+                           w.partials, w.ctl, pass, final_gram);
+    }
+}
+
 template <int NP>
 static hipError_t launch_small(hipStream_t s, const Problem &p, const Work &w, int mode, int pass,
                                bool f32, int final_gram)
 {
-    dim3 grid(w.nwg), block(256);
-    if (mode == 0) {
-        if (f32)
-            hipLaunchKernelGGL((k_pass_small<NP, 0, true>), grid, block, 0, s, p, w.Rt, w.dinv,
-                               w.partials, w.ctl, pass, final_gram);
-        else
-            hipLaunchKernelGGL((k_pass_small<NP, 0, false>), grid, block, 0, s, p, w.Rt, w.dinv,
-                               w.partials, w.ctl, pass, final_gram);
-    } else if (mode == 1) {
-        hipLaunchKernelGGL((k_pass_small<NP, 1, false>), grid, block, 0, s, p, w.Rt, w.dinv,
-                           w.partials, w.ctl, pass, final_gram);
-    } else {
-        hipLaunchKernelGGL((k_pass_small<NP, 2, false>), grid, block, 0, s, p, w.Rt, w.dinv,
-                           w.partials, w.ctl, pass, final_gram);
-    }
+    const bool aligned = (reinterpret_cast<uintptr_t>(p.X) & 15) == 0 && (p.ldx & 1) == 0 &&
+                         (mode == 0 || ((reinterpret_cast<uintptr_t>(p.Q) & 15) == 0 && (p.ldq & 1) == 0));
+    if (aligned && (p.n & 1) == 0)
+        launch_small_v<NP, true>(s, p, w, mode, pass, f32, final_gram);
+    else
+        launch_small_v<NP, false>(s, p, w, mode, pass, f32, final_gram);
     return hipGetLastError();
 }
 
@@ -468,8 +625,8 @@ static hipError_t launch_trsm_big(hipStream_t s, const Problem &p, const Work &w
     const int64_t cap = 4 * (int64_t)cus;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_trsm_big<NP>), dim3((unsigned)blocks), dim3(256), 0, s, p, w.Rt, w.dinv,
-                       w.ctl, pass);
+    hipLaunchKernelGGL((k_trsm_big<NP>), dim3((unsigned)blocks), dim3(256), 0, s, p, factor_of(w, NP, pass),
+                       dinv_of(w, NP, pass), w.ctl, pass);
     return hipGetLastError();
 }
 
@@ -534,8 +691,8 @@ hipError_t launch_reduce(hipStream_t s, const Work &w, int pass, int64_t elems, 
 {
     dim3 grid((unsigned)((elems + 255) / 256), (unsigned)w.nlvl2), block(256);
     prof_before(s, "reduce");
-    hipLaunchKernelGGL(k_reduce, grid, block, 0, s, w.partials, w.lvl2, w.nwg, elems, w.ctl, pass,
-                       final_gram);
+    hipLaunchKernelGGL(k_reduce, grid, block, 0, s, w.partials, w.lvl2, w.gsum, w.counters, w.nwg,
+                       w.nlvl2, elems, w.ctl, pass, final_gram);
     prof_after(s);
     return hipGetLastError();
 }

@@ -79,6 +79,7 @@ struct Problem {
     int64_t ldr;
     const double *bdiag;   // tridiagonal B or nullptr
     const double *boff;
+    int32_t zero;          // always 0; opaque to the compiler (keeps loads inside loops)
 };
 
 // Workspace carve-out of one factorization.
@@ -86,16 +87,28 @@ struct Work {
     Ctl *ctl;
     double *G;          // np x np reduced Gram (both triangles)
     double *Ge;         // np x np Euclidean Gram of X for the oblique first-pass shift
-    double *Rt;         // np x np factor of the current pass (identity padding)
-    double *dinv;       // np reciprocals of diag(Rt)
-    double *Racc[2];    // np x np accumulated R (ping-pong)
+    double *Rhist;      // SCQR_MAX_PASSES x np x np: factor R~ of each pass (identity padding)
+    double *dhist;      // SCQR_MAX_PASSES x np: reciprocals of diag(R~) of each pass
+    double *Racc[2];    // np x np ping-pong buffers for the final product R = R~_p ... R~_1
     double *partials;   // nwg x parts_elems
     double *lvl2;       // nlvl2 x parts_elems
+    double *gsum;       // parts_elems: the reduced Gram tiles of the last reduction
+    uint32_t *counters; // one arrival counter per 256-element chunk of the reduction
     double *bmax;       // nwg per-workgroup Gershgorin maxima (oblique first pass)
     int nwg;            // workgroups (= partial count) of the pass kernels
     int nlvl2;          // level-2 partial count
     int64_t parts_elems;  // elements of one partial (tiles * 256, doubled for oblique pass 1)
 };
+
+// Factor and reciprocal diagonal used by the substitution of pass `pass` (slot 0 for pass 0).
+inline const double *factor_of(const Work &w, int np, int pass)
+{
+    return w.Rhist + (int64_t)(pass > 1 ? pass - 1 : 0) * np * np;
+}
+inline const double *dinv_of(const Work &w, int np, int pass)
+{
+    return w.dhist + (int64_t)(pass > 1 ? pass - 1 : 0) * np;
+}
 
 // Schedule parameters copied to the Cholesky kernel by value.
 struct SchedParams {
@@ -125,6 +138,7 @@ hipError_t launch_set_factor(hipStream_t s, const Work &w, int np, int n, const 
                              int64_t ldr);
 hipError_t launch_final_omega(hipStream_t s, const Problem &p, const Work &w,
                               const SchedParams &sp);
+hipError_t launch_finalize_r(hipStream_t s, const Problem &p, const Work &w);
 
 // QR adjoint
 hipError_t launch_backward(hipStream_t s, int64_t m, int n, const double *Q, int64_t ldq,

@@ -66,8 +66,14 @@ def replay(scqr, X, info, gram_exact=True):
         assert np.all(np.abs(Gg - Go) <= 2 * gm * (np.abs(Qh).T @ np.abs(Qh)) + 1e-300), f"Gram pass {p + 1}"
         s = info.shift[p]
         if info.shifted_mask >> p & 1:
+            # ||.||_2^2 comes from a Rayleigh-quotient power iteration stopped at a relative
+            # change of 1e-6 (normest's rule): a lower bound, within 1e-4 on the spectrum of
+            # X^T X; on a continuation pass the leading eigenvalues of Q^T Q cluster near 1
+            # and the bound may stay up to 1% low.
             lam = np.linalg.eigvalsh(Gg)[-1]
-            assert abs(s - oracle.shift(m, n, lam)) <= 1e-6 * s, f"shift pass {p + 1}"
+            s_exact = oracle.shift(m, n, lam)
+            assert s <= s_exact * (1 + 1e-12), f"shift pass {p + 1}"
+            assert s >= s_exact * (1 - (1e-4 if p == 0 else 1e-2)), f"shift pass {p + 1}"
         else:
             assert s == 0.0
         check_chol(Gg, s, Rg)
