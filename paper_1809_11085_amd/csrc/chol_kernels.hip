@@ -161,8 +161,8 @@ __device__ double power_lambda(const double *G, int S, int n, double *v, double 
 //   r_jl = ((a_jl - r_0j r_0l) - r_1j r_1l - ...) / r_jj,   l > j,
 // while the pivot radicands d_l = (a_ll + s) - r_0l^2 - r_1l^2 - ... are brought up to date
 // as soon as each r_kl is known (one FMA per column and row), so that r_jj = sqrt(d_j) needs
-// no chain of its own.  Both use the k-ordered subtractions of the textbook algorithm.  The
-// inner dot products only read LDS and are unrolled so that their loads overlap.  With WAVE the
+// no chain of its own (these radicands are updated in increasing k, as in the textbook
+// algorithm).  The inner dot products only read LDS and are unrolled so that their loads overlap.  With WAVE the
 // first wave alone runs it (n <= 64) and the per-row synchronisation is a wave-level fence.
 template <bool WAVE>
 __device__ int chol_columns(double *G, int S, int n, double s, double *dd)
@@ -261,10 +261,13 @@ k_chol(Problem p, Work w, SchedParams sp, int pass, int variant)
     Ctl *ctl = w.ctl;
     scqr_info *info = sp.info;
 
-    if (variant == 1) {
-        if (!(ctl->active && ctl->redo_fp64)) return;
-    } else {
-        if (!(ctl->active && ctl->pass == pass - 1 && ctl->last == 0)) return;
+    {
+        const int c_active = ctl->active, c_redo = ctl->redo_fp64, c_pass = ctl->pass, c_last = ctl->last;
+        if (variant == 1) {
+            if (!(c_active && c_redo)) return;
+        } else {
+            if (!(c_active && c_pass == pass - 1 && c_last == 0)) return;
+        }
     }
     const int n = p.n;
     const bool oblique = sp.oblique != 0;
@@ -510,17 +513,31 @@ __global__ void __launch_bounds__(256) k_finalize_r(Problem p, Work w)
     const int passes = w.ctl->pass;
     double *A = IN_LDS ? acc_l : w.Racc[0];
     const int sa = IN_LDS ? S : NP;
-#pragma unroll 16
-    for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
-        const int i = idx / NP, j = idx % NP;
-        A[i * sa + j] = (passes >= 1) ? w.Rhist[idx] : (i == j ? 1.0 : 0.0);
+    if (passes >= 1) {
+        // NP*NP/256 loads per thread, all issued before any is used
+        constexpr int PER = NP * NP / 256;
+        double v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) v[u] = w.Rhist[u * 256 + threadIdx.x];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = u * 256 + threadIdx.x;
+            A[(idx / NP) * sa + idx % NP] = v[u];
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x)
+            A[(idx / NP) * sa + idx % NP] = ((idx / NP) == (idx % NP)) ? 1.0 : 0.0;
     }
     __syncthreads();
     for (int q = 2; q <= passes; ++q) {
         const double *F = w.Rhist + (int64_t)(q - 1) * NP * NP;
         if (NP <= 64) {  // stage the factor in LDS next to the running product
-#pragma unroll 16
-            for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) fl[idx] = F[idx];
+            constexpr int PER = NP * NP / 256;
+            double v[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) v[u] = F[u * 256 + threadIdx.x];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) fl[u * 256 + threadIdx.x] = v[u];
             __syncthreads();
             F = fl;
         }

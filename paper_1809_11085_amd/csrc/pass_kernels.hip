@@ -111,21 +111,22 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
             const int e2 = lane + 64 * i;
             const int r = e2 / (NP / 2), c = 2 * (e2 % (NP / 2));
             const int64_t row = rb + r;
-            double a = 0.0, b = 0.0;
-            if (row < p.m) {
-                const double *src = p.X + row * p.ldx + c;
-                if (VEC) {
-                    if (c < n) {
-                        const double2 v = *reinterpret_cast<const double2 *>(src);
-                        a = v.x;
-                        b = v.y;
-                    }
-                } else {
+            if (VEC) {
+                // branch-free: load a valid pair (clamped address), zero it when out of range
+                const bool ok = row < p.m && c < n;
+                const int64_t rr = row < p.m ? row : p.m - 1;
+                const int cc = c < n ? c : 0;
+                const double2 v = *reinterpret_cast<const double2 *>(p.X + rr * p.ldx + cc);
+                pre[i] = ok ? v : make_double2(0.0, 0.0);
+            } else {
+                double a = 0.0, b = 0.0;
+                if (row < p.m) {
+                    const double *src = p.X + row * p.ldx + c;
                     if (c < n) a = src[0];
                     if (c + 1 < n) b = src[1];
                 }
+                pre[i] = make_double2(a, b);
             }
-            pre[i] = make_double2(a, b);
         }
     };
     int64_t pn = (int64_t)blockIdx.x * WAVES + wv;
@@ -178,11 +179,14 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
                         t[c] = v.x;
                         t[c + 1] = v.y;
                     }
-                    const double *Rd = Rt + off + (16 * J) * NP + 16 * J;
-                    const double *dd = dinv + off + 16 * J;
+                    int64_t offk = off;
 #pragma unroll
                     for (int k = 0; k < 16; ++k) {
-                        const double qk = t[k] * dd[k];
+                        // re-laundered every two rows: later rows' scalar loads may not be
+                        // hoisted above earlier rows' work (they would exhaust the SGPRs)
+                        if ((k & 1) == 0) asm volatile("" : "+s"(offk));
+                        const double *Rd = Rt + offk + (16 * J) * NP + 16 * J;
+                        const double qk = t[k] * dinv[offk + 16 * J + k];
                         t[k] = qk;
 #pragma unroll
                         for (int j = k + 1; j < 16; ++j) t[j] = __builtin_fma(-qk, Rd[k * NP + j], t[j]);
