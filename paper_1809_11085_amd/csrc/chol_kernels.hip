@@ -79,6 +79,125 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Broadcast lane `src`'s double to every lane (two 32-bit readlanes; src is wave-uniform).
+__device__ __forceinline__ double readlane_d(double v, int src)
+{
+    const unsigned long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, src);
+    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+    return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const unsigned long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wave, the same value in every lane: within each row of 16 lanes
+// by DPP exchanges (quad xor 1, quad xor 2, half-row mirror, row mirror; each lane adds the
+// same two operands, so every lane of a row holds the identical row sum), then the four row
+// sums ((r0 + r1) + (r2 + r3)).  Fixed order, so the result is deterministic.
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_d<0x141>(v);  // row_half_mirror
+    v += dpp_d<0x140>(v);  // row_mirror
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// Power iteration of the first wave for NP <= 64 with row i of G held in lane i's registers
+// and the iterate broadcast from LDS (same rule and start vector as power_lambda_wave).
+template <int NP>
+__device__ double power_lambda_regs(const double *G, int S, int n, double *v)
+{
+    const int lane = threadIdx.x & 63;
+    const int row = lane < NP ? lane : NP - 1;
+    const bool act = lane < n;
+    double g[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) g[k] = (act && k < n) ? G[row * S + k] : 0.0;
+    double vi = act ? 1.0 / sqrt((double)n) : 0.0;
+    if (lane < NP) v[lane] = vi;
+    wave_sync_c();
+    double lam = 0.0;
+    for (int it = 0; it < 100; ++it) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+        for (int k = 0; k + 4 <= NP; k += 4) {
+            a0 = __builtin_fma(g[k], v[k], a0);
+            a1 = __builtin_fma(g[k + 1], v[k + 1], a1);
+            a2 = __builtin_fma(g[k + 2], v[k + 2], a2);
+            a3 = __builtin_fma(g[k + 3], v[k + 3], a3);
+        }
+        const double y = (a0 + a1) + (a2 + a3);
+        const double vy = wave_sum_dpp(vi * y);
+        const double yy = wave_sum_dpp(y * y);
+        const double prev = lam;
+        lam = vy;
+        if (!(yy > 0.0)) break;
+        const double inv = 1.0 / sqrt(yy);
+        vi = y * inv;
+        wave_sync_c();
+        if (lane < NP) v[lane] = vi;
+        wave_sync_c();
+        if (it > 0 && fabs(lam - prev) <= 1e-6 * fabs(lam)) break;
+    }
+    return lam;
+}
+
+// Upper Cholesky of G + sI for NP <= 64 by the first wave, right-looking with the trailing
+// columns in registers: lane l keeps rows j.. of column l (c[0] = entry (j, l)).  Step j takes
+// the pivot radicand from lane j, r_jj = sqrt, r_jl = c[0] / r_jj, writes row j of R into G,
+// broadcasts it through rb (2 NP doubles, upper half zero) and subtracts r_jk r_jl from every
+// remaining entry (k, l) while shifting the rows down by one.  Each entry therefore receives
+// exactly the subtractions a_kl - r_0k r_0l - r_1k r_1l - ... in increasing order followed by
+// one division, as in the textbook algorithm.  Entries below the diagonal are not meaningful and
+// are never read.  Returns 0 or 1 + the column whose radicand was <= 0 or not finite.
+template <int NP>
+__device__ int chol_wave_regs(double *G, int S, int n, double s, double *rb)
+{
+    static_assert(NP <= 64, "one column per lane");
+    const int l = threadIdx.x & 63;
+    const int col = l < NP ? l : NP - 1;
+    double c[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const double a = G[k * S + col];
+        c[k] = (k == l) ? a + s : a;
+    }
+#pragma unroll
+    for (int i = 0; i < 2 * NP; i += 64)
+        if (i + l < 2 * NP) rb[i + l] = 0.0;
+    wave_sync_c();
+    for (int j = 0; j < n; ++j) {
+        const double d = readlane_d(c[0], j);
+        if (!(d > 0.0) || !isfinite(d)) return j + 1;
+        const double rjj = sqrt(d);
+        const double r = (l == j) ? rjj : c[0] / rjj;
+        if (l < NP) {
+            G[j * S + l] = r;
+            rb[l] = r;
+        }
+        wave_sync_c();
+        const double *rr = rb + j + 1;
+        // only rows below n matter: chunks of 16 rows past n - 1 - j are skipped
+#pragma unroll
+        for (int q = 0; q < NP; q += 16) {
+            if (q > 0 && q > n - 2 - j) break;
+#pragma unroll
+            for (int k = q; k < q + 16 && k + 1 < NP; ++k) c[k] = __builtin_fma(-rr[k], r, c[k + 1]);
+        }
+        c[NP - 1] = 0.0;
+        wave_sync_c();
+    }
+    return 0;
+}
+
 // Rayleigh-quotient power iteration for lambda_max of the symmetric n x n matrix G (stride S),
 // run by the first wave alone (no workgroup barriers): start vector 1/sqrt(n), at most 100
 // iterations, stop when the quotient changes by <= 1e-6 relative (the stopping rule of the normest
@@ -146,7 +265,11 @@ __device__ double power_lambda(const double *G, int S, int n, double *v, double 
 {
     __syncthreads();
     if (threadIdx.x < 64) {
-        const double lam = power_lambda_wave<NP>(G, S, n, v);
+        double lam;
+        if constexpr (NP <= 64)
+            lam = power_lambda_regs<NP>(G, S, n, v);
+        else
+            lam = power_lambda_wave<NP>(G, S, n, v);
         if (threadIdx.x == 0) red[15] = lam;
     }
     __syncthreads();
@@ -214,11 +337,11 @@ __device__ int chol_columns(double *G, int S, int n, double s, double *dd)
 template <int NP>
 __device__ int chol_inplace(double *G, int S, int n, double s, double *red, double *dd)
 {
-    if (NP <= 64) {
+    if constexpr (NP <= 64) {
         __syncthreads();
         int bd = 0;
         if (threadIdx.x < 64) {
-            bd = chol_columns<true>(G, S, n, s, dd);
+            bd = chol_wave_regs<NP>(G, S, n, s, dd);
             if (threadIdx.x == 0) red[14] = (double)bd;
         }
         __syncthreads();
@@ -257,7 +380,7 @@ k_chol(Problem p, Work w, SchedParams sp, int pass, int variant)
     constexpr bool IN_LDS = NP <= 128;
     constexpr int S = NP + 1;
     __shared__ double lds[IN_LDS ? NP * S : 1];
-    __shared__ double vbuf[NP], ybuf[NP], red[16];
+    __shared__ double vbuf[NP], ybuf[2 * NP], red[16];
     Ctl *ctl = w.ctl;
     scqr_info *info = sp.info;
 
@@ -501,8 +624,79 @@ __global__ void __launch_bounds__(256) k_set_factor(Work w, int n, const double 
 // written to the caller's R with a zero lower triangle; the identity if no pass was applied.
 // One workgroup; the running product stays in LDS when it fits, each entry of a product is a
 // sum over k = i..j taken in four interleaved partial sums.
+// NP <= 64: thread t owns column j = t % NP of rows g*ROWS .. g*ROWS+ROWS-1 (g = t / NP) of
+// each product and accumulates all of them at once over k = 0..NP-1.  Both factors are upper
+// triangular with identity padding, so the terms outside i <= k <= j are exact zeros and every
+// entry is the k-ordered sum over i..j.  The next factor is loaded while the current product runs.
 template <int NP>
-__global__ void __launch_bounds__(256) k_finalize_r(Problem p, Work w)
+__device__ void finalize_small(const Problem &p, const Work &w, int passes)
+{
+    constexpr int S = NP + 1;       // running product, row-major
+    constexpr int ST = NP + 2;      // factor transposed: ft[k * ST + i] = F[i][k]
+    constexpr int GR = 256 / NP;    // row groups
+    constexpr int ROWS = NP / GR;   // rows per thread
+    constexpr int PER = NP * NP / 256;
+    __shared__ double A[NP * S];
+    __shared__ __attribute__((aligned(16))) double ft[NP * ST];
+    const int t = threadIdx.x, j = t % NP, g = t / NP;
+    const int n = p.n;
+
+    double nx[PER];
+    if (passes >= 1) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) nx[u] = w.Rhist[u * 256 + t];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) A[((u * 256 + t) / NP) * S + (u * 256 + t) % NP] = nx[u];
+    } else {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = u * 256 + t;
+            A[(idx / NP) * S + idx % NP] = (idx / NP == idx % NP) ? 1.0 : 0.0;
+        }
+    }
+    if (passes >= 2) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) nx[u] = w.Rhist[(int64_t)NP * NP + u * 256 + t];
+    }
+    for (int q = 2; q <= passes; ++q) {
+        __syncthreads();  // previous product written to A, previous factor no longer read
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = u * 256 + t;
+            ft[(idx % NP) * ST + idx / NP] = nx[u];
+        }
+        if (q < passes) {
+            const double *Fn = w.Rhist + (int64_t)q * NP * NP;
+#pragma unroll
+            for (int u = 0; u < PER; ++u) nx[u] = Fn[u * 256 + t];
+        }
+        __syncthreads();
+        double acc[ROWS];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) acc[r] = 0.0;
+#pragma unroll 4
+        for (int k = 0; k < NP; ++k) {
+            const double a = A[k * S + j];
+            const double *fk = ft + k * ST + g * ROWS;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) acc[r] = __builtin_fma(fk[r], a, acc[r]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) A[(g * ROWS + r) * S + j] = acc[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = u * 256 + t;
+        const int i = idx / NP, jj = idx % NP;
+        if (i < n && jj < n) p.R[(int64_t)i * p.ldr + jj] = (jj >= i) ? A[i * S + jj] : 0.0;
+    }
+}
+
+// NP >= 128: the running product in LDS (NP = 128) or in the global ping-pong buffers.
+template <int NP>
+__device__ void finalize_big(const Problem &p, const Work &w)
 {
     constexpr bool IN_LDS = NP <= 128;
     constexpr int S = NP + 1;
@@ -582,6 +776,15 @@ __global__ void __launch_bounds__(256) k_finalize_r(Problem p, Work w)
         const int i = idx / NP, j = idx % NP;
         if (i < n && j < n) p.R[(int64_t)i * p.ldr + j] = (j >= i) ? A[i * sa + j] : 0.0;
     }
+}
+
+template <int NP>
+__global__ void __launch_bounds__(256) k_finalize_r(Problem p, Work w)
+{
+    if constexpr (NP <= 64)
+        finalize_small<NP>(p, w, w.ctl->pass);
+    else
+        finalize_big<NP>(p, w);
 }
 
 // ||G - I||_F of the final Gram (final_gram option).
