@@ -6,7 +6,15 @@ Default workload: X = U diag(sigma) V^T with m = 2^22, n = 64, sigma geometric f
 Algorithm 2 continuation) with the paper's shift (eq:finds2).  One step = one complete
 factorization X -> (Q, R) with X resident in HBM.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2|c2b|c1|c3|c5]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2|c2b|c1|c3] [--no-extras]
+
+With the default workload the line also carries ``extras``, timed with HIP events on the
+launch stream (inputs generated on the host by the seeded generators, then resident in HBM):
+  c2b  CholeskyQR2 vs shiftedCholeskyQR3 (Algorithm 3) at kappa = 1e6 (same accuracy bar);
+  c3   oblique factorization, 1e6 x 128, kappa = 1e13, tridiagonal SPD B;
+  c4   512 uneven instances (m_i in [1e4, 2e5], n_i in {16, 32, 64, 128}, kappa_i in
+       [1e4, 1e15]): one batched call vs a loop of single calls, and FP32-first vs FP64;
+  c5   2^20 x 256, kappa = 1e8: forward (Algorithm 3) and the hand-written adjoint.
 
 The throughput counts the algorithmic flops of the passes actually executed,
 passes * (m n (n+1) + m n^2) (one Gram and one triangular solve per pass).  The roofline
@@ -92,6 +100,141 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
     print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}))
 
 
+def _time_ms(fn, reps=3, warmup=1):
+    """Median over reps of the HIP-event time of fn() on the current stream (ms)."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        fn()
+        b.record(st)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def flops_of(m, n, passes):
+    return passes * (m * n * (n + 1) + m * n * n)
+
+
+def extra_c2b(scqr, synth):
+    import torch
+
+    m, n = 1 << 22, 64
+    X = torch.from_numpy(synth.randsvd(m, n, 1e6, seed=synth.seed_for(1, 2))).cuda()
+    out = {}
+    for sched in ("fixed3", "cholqr2"):
+        plan = scqr.Plan(m, n, "cuda", schedule=sched)
+        ms = _time_ms(lambda: plan.run(X), reps=5)
+        info = plan.read_info()
+        out[sched] = {"ms": round(ms, 4), "passes": info.passes, "status": scqr.status_string(info.status),
+                      "TFLOP/s": round(flops_of(m, n, info.passes) / ms / 1e9, 3)}
+        del plan
+    out["speedup_cholqr2_vs_scholqr3"] = round(out["fixed3"]["ms"] / out["cholqr2"]["ms"], 3)
+    del X
+    torch.cuda.empty_cache()
+    return out
+
+
+def extra_c3(scqr, synth):
+    import torch
+
+    m, n = 1000000, 128
+    X = torch.from_numpy(synth.randsvd(m, n, 1e13, seed=synth.seed_for(2))).cuda()
+    d, o = synth.tridiag_b(m, seed=synth.seed_for(2, 1))
+    B = (torch.from_numpy(d).cuda(), torch.from_numpy(o).cuda())
+    plan = scqr.Plan(m, n, "cuda", B=B, schedule="adaptive")
+    ms = _time_ms(lambda: plan.run(X), reps=5)
+    info = plan.read_info()
+    fl = flops_of(m, n, info.passes) + info.passes * 5 * m * n
+    res = {"ms": round(ms, 4), "passes": info.passes, "status": scqr.status_string(info.status),
+           "TFLOP/s": round(fl / ms / 1e9, 3), "frac_fp64_peak": round(fl / ms / 1e9 / FP64_PEAK_TFS, 4),
+           "shift": info.shift[0], "bnorm": info.bnorm}
+    del plan, X
+    torch.cuda.empty_cache()
+    return res
+
+
+def extra_c4(scqr, synth):
+    import torch
+
+    spec = synth.batch_spec(512)
+    shapes = [(s.m, s.n) for s in spec]
+    t0 = time.perf_counter()
+    Xs = [torch.from_numpy(synth.randsvd(s.m, s.n, s.kappa, seed=s.seed)).cuda() for s in spec]
+    torch.cuda.synchronize()
+    log(f"[bench] c4: generated 512 instances in {time.perf_counter() - t0:.1f} s")
+    res = {"instances": len(spec), "sum_mn": int(sum(m * n for m, n in shapes))}
+    # loop of single calls (each with its own pre-allocated plan)
+    plans = [scqr.Plan(m, n, "cuda") for m, n in shapes]
+
+    def loop():
+        for pl, X in zip(plans, Xs):
+            pl.run(X)
+
+    ms_loop = _time_ms(loop, reps=3)
+    passes_loop = [pl.read_info().passes for pl in plans]
+    del plans
+    torch.cuda.empty_cache()
+    bp = scqr.BatchedPlan(shapes, "cuda")
+    ms_b = _time_ms(lambda: bp.run(Xs), reps=5)
+    infos = bp.read_infos()
+    passes = [i.passes for i in infos]
+    fl = sum(flops_of(m, n, p) for (m, n), p in zip(shapes, passes))
+    res["loop_ms"] = round(ms_loop, 3)
+    res["batched_ms"] = round(ms_b, 3)
+    res["speedup_batched_vs_loop"] = round(ms_loop / ms_b, 3)
+    res["batched_TFLOP/s"] = round(fl / ms_b / 1e9, 3)
+    res["ok"] = sum(1 for i in infos if i.status == scqr.OK)
+    res["passes_hist"] = {str(k): passes.count(k) for k in sorted(set(passes))}
+    res["passes_equal_loop"] = sum(1 for a, b in zip(passes, passes_loop) if a == b)
+    del bp
+    torch.cuda.empty_cache()
+    bm = scqr.BatchedPlan(shapes, "cuda", precision="fp32_first")
+    ms_m = _time_ms(lambda: bm.run(Xs), reps=5)
+    im = bm.read_infos()
+    res["mixed_batched_ms"] = round(ms_m, 3)
+    res["speedup_mixed_vs_fp64_batched"] = round(ms_b / ms_m, 3)
+    res["mixed_ok"] = sum(1 for i in im if i.status == scqr.OK)
+    res["mixed_fell_back"] = sum(1 for i in im if i.fell_back_fp64)
+    del bm, Xs
+    torch.cuda.empty_cache()
+    return res
+
+
+def extra_c5(scqr, synth):
+    import torch
+
+    m, n = 1 << 20, 256
+    X = torch.from_numpy(synth.randsvd(m, n, 1e8, seed=synth.seed_for(5))).cuda()
+    dq, dr = synth.upstream_grads(m, n, seed=synth.seed_for(5, 1))
+    dQ, dR = torch.from_numpy(dq).cuda(), torch.from_numpy(dr).cuda()
+    del dq, dr
+    plan = scqr.Plan(m, n, "cuda", schedule="fixed3")
+    dX = torch.empty_like(X)
+    Q, R = plan.run(X)
+    ms_fwd = _time_ms(lambda: plan.run(X), reps=3)
+    ms_bwd = _time_ms(lambda: scqr.qr_backward(Q, R, dQ, dR, out=dX), reps=3)
+    info = plan.read_info()
+    fl_f = flops_of(m, n, info.passes)
+    fl_b = 5 * m * n * n
+    res = {"forward_ms": round(ms_fwd, 3), "backward_ms": round(ms_bwd, 3), "passes": info.passes,
+           "status": scqr.status_string(info.status),
+           "forward_TFLOP/s": round(fl_f / ms_fwd / 1e9, 3), "backward_TFLOP/s": round(fl_b / ms_bwd / 1e9, 3),
+           "backward_GB/s": round(40 * m * n / ms_bwd / 1e6, 1),
+           "backward_over_forward": round(ms_bwd / ms_fwd, 3)}
+    del plan, X, dQ, dR, dX, Q, R
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +244,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="c2b,c3,c4,c5")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -223,6 +368,22 @@ def main():
         result["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         result["cpu_baseline"]["value"] = round(cb["value"], 5)
         log(f"[bench] cpu baseline: {cb['value'] * 1e3:.2f} GFLOP/s on {cb['cores']} threads")
+    if args.workload == "c2" and not args.no_extras:
+        fns = {"c2b": extra_c2b, "c3": extra_c3, "c4": extra_c4, "c5": extra_c5}
+        extras, speed = {}, {}
+        for name in [x for x in args.extras.split(",") if x]:
+            t = time.perf_counter()
+            try:
+                extras[name] = fns[name](scqr, synth)
+            except Exception as exc:  # an extra never hides the headline line
+                extras[name] = {"error": f"{type(exc).__name__}: {exc}"}
+            log(f"[bench] extra {name}: {extras[name]} ({time.perf_counter() - t:.1f} s)")
+        for name, key in (("c4", "speedup_batched_vs_loop"), ("c4", "speedup_mixed_vs_fp64_batched"),
+                          ("c2b", "speedup_cholqr2_vs_scholqr3")):
+            if key in extras.get(name, {}):
+                speed[f"{name}_{key[8:]}"] = extras[name][key]
+        result["speedups"] = speed
+        result["extras"] = extras
     print(json.dumps(result), flush=True)
 
 

@@ -321,6 +321,52 @@ def qr_batched(Xs, *, inplace=False, check=True, **opts):
     return Qs, Rs, [decode_info(infos[i]) for i in range(b)]
 
 
+class BatchedPlan:
+    """Pre-allocated workspace, outputs and pointer tables for repeated batched factorizations
+    of one list of shapes (``run`` allocates nothing)."""
+
+    def __init__(self, shapes, device="cuda", inplace=False, **opts):
+        self.dev = torch.device(device)
+        self.shapes = [(int(m), int(n)) for m, n in shapes]
+        self.b = len(self.shapes)
+        self.inplace = inplace
+        self.opts = _opts(**opts)
+        self.ms = (ctypes.c_int64 * self.b)(*[m for m, _ in self.shapes])
+        self.ns = (ctypes.c_int64 * self.b)(*[n for _, n in self.shapes])
+        sz = ctypes.c_size_t()
+        _check(lib().scqr_batched_workspace_bytes(self.b, self.ms, self.ns, ctypes.byref(self.opts),
+                                                  ctypes.byref(sz)), "scqr_batched_workspace_bytes")
+        self.ws_bytes = sz.value
+        self._ws_buf, self.ws = _workspace(self.ws_bytes, self.dev)
+        self.Qs = None if inplace else [torch.empty((m, n), dtype=torch.float64, device=self.dev)
+                                        for m, n in self.shapes]
+        self.Rs = [torch.empty((n, n), dtype=torch.float64, device=self.dev) for _, n in self.shapes]
+        self.infos = torch.zeros((self.b, INFO_BYTES), dtype=torch.uint8, device=self.dev)
+        self._rp = (ctypes.c_void_p * self.b)(*[R.data_ptr() for R in self.Rs])
+        self._qp = None if inplace else (ctypes.c_void_p * self.b)(*[Q.data_ptr() for Q in self.Qs])
+        self._xkey = None
+
+    def run(self, Xs):
+        if len(Xs) != self.b:
+            raise ValueError("batch size does not match the plan")
+        key = tuple(X.data_ptr() for X in Xs)
+        if key != self._xkey:
+            for X, (m, n) in zip(Xs, self.shapes):
+                _mat(X, "X")
+                if tuple(X.shape) != (m, n) or not X.is_contiguous():
+                    raise ValueError("batched X_i must be contiguous and match the plan's shapes")
+            self._xp = (ctypes.c_void_p * self.b)(*key)
+            self._xkey = key
+        qp = self._xp if self.inplace else self._qp
+        _check(lib().scqr_qr_batched(_stream(self.dev), self.b, self.ms, self.ns, self._xp, qp, self._rp,
+                                     self.ws, self.ws_bytes, ctypes.byref(self.opts), self.infos.data_ptr()),
+               "scqr_qr_batched")
+        return (Xs if self.inplace else self.Qs), self.Rs
+
+    def read_infos(self):
+        return [decode_info(self.infos[i]) for i in range(self.b)]
+
+
 def qr_backward(Q: torch.Tensor, R: torch.Tensor, dQ: torch.Tensor = None,
                 dR: torch.Tensor = None, out: torch.Tensor = None) -> torch.Tensor:
     """dX = (dQ + Q copyltu(M)) R^{-T}, M = R dR^T - dQ^T Q (None gradients count as zero)."""

@@ -35,7 +35,7 @@ void prof_before(hipStream_t s, const char *name)
     if (!g_prof_on.load(std::memory_order_relaxed)) return;
     hipEvent_t a;
     if (hipEventCreate(&a) != hipSuccess) return;
-    hipEventRecord(a, s);
+    (void)hipEventRecord(a, s);
     t_pending_a = a;
     t_pending_name = name;
 }
@@ -44,7 +44,7 @@ void prof_after(hipStream_t s)
     if (!g_prof_on.load(std::memory_order_relaxed) || !t_pending_a) return;
     hipEvent_t b;
     if (hipEventCreate(&b) != hipSuccess) return;
-    hipEventRecord(b, s);
+    (void)hipEventRecord(b, s);
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof.push_back({t_pending_name, t_pending_a, b});
     t_pending_a = nullptr;
@@ -151,6 +151,136 @@ scqr_status check_B(const scqr_spd_op *B, int64_t m)
 }
 
 scqr_status hip_status(hipError_t e) { return e == hipSuccess ? SCQR_OK : SCQR_E_HIP; }
+
+// ---------------------------------------------------------------- batched planning
+// Instances are grouped by padded width; every class is one launch per step.  A class's rows
+// are cut into tasks of equal size (a multiple of 32 rows, at least kBatchMinRows) so that a
+// launch has about kBatchTargetTasks workgroups; an instance's tasks are contiguous.  The plan
+// depends only on (m_i, n_i) and the options.
+constexpr int kNumClasses = 5;
+constexpr int kClassNp[kNumClasses] = {16, 32, 64, 128, 256};
+constexpr int64_t kBatchTargetTasks = 1024;
+constexpr int64_t kBatchMinRows = 1024;
+
+int class_of(int64_t n)
+{
+    const int np = padded_n(n);
+    for (int c = 0; c < kNumClasses; ++c)
+        if (kClassNp[c] == np) return c;
+    return -1;
+}
+
+struct BatchPlan {
+    int P = 0, slots = 0;
+    std::vector<int> order;           // instance indices, class-major, ascending within a class
+    int cls_first[kNumClasses + 1] = {};
+    std::vector<int32_t> ntask;       // per instance
+    int64_t rows_per_task[kNumClasses] = {};
+    int task_first[kNumClasses + 1] = {};
+    std::vector<size_t> inst_off;     // per instance: offset of its block in the workspace
+    size_t off_inst = 0, off_task = 0, off_blocks = 0, off_part[kNumClasses] = {}, total = 0;
+};
+
+size_t inst_block_bytes(int np, int slots)
+{
+    size_t b = align256(sizeof(Ctl));
+    b += align256(sizeof(double) * np * np * slots);
+    b += align256(sizeof(double) * np * slots);
+    b += align256(sizeof(double) * (size_t)pass_partial_elems(np, false));
+    if (np > 128) b += align256(sizeof(double) * np * (np + 1)) + 2 * align256(sizeof(double) * np * np);
+    return b;
+}
+
+scqr_status plan_batch(int32_t batch, const int64_t *m, const int64_t *n, const scqr_opts &o, BatchPlan &bp)
+{
+    scqr_status st = check_opts(&o);
+    if (st != SCQR_OK) return st;
+    for (int32_t i = 0; i < batch; ++i) {
+        if (n[i] < 1 || m[i] < n[i]) return SCQR_E_INVALID;
+        if (n[i] > SCQR_MAX_N) return SCQR_E_UNSUPPORTED;
+    }
+    bp.P = o.schedule == SCQR_SCHED_FIXED3 ? 3 : o.schedule == SCQR_SCHED_CHOLQR2 ? 2 : o.max_passes;
+    bp.slots = bp.P;
+    bp.ntask.assign(batch, 0);
+    bp.inst_off.assign(batch, 0);
+    int ntasks = 0;
+    for (int c = 0; c < kNumClasses; ++c) {
+        bp.cls_first[c] = (int)bp.order.size();
+        bp.task_first[c] = ntasks;
+        int64_t rows = 0;
+        for (int32_t i = 0; i < batch; ++i)
+            if (class_of(n[i]) == c) {
+                bp.order.push_back(i);
+                rows += m[i];
+            }
+        int64_t rpt = (rows + kBatchTargetTasks - 1) / kBatchTargetTasks;
+        rpt = (rpt + kBatchRowAlign - 1) / kBatchRowAlign * kBatchRowAlign;
+        if (rpt < kBatchMinRows) rpt = kBatchMinRows;
+        bp.rows_per_task[c] = rpt;
+        for (int k = bp.cls_first[c]; k < (int)bp.order.size(); ++k) {
+            const int i = bp.order[k];
+            bp.ntask[i] = (int32_t)((m[i] + rpt - 1) / rpt);
+            ntasks += bp.ntask[i];
+        }
+    }
+    bp.cls_first[kNumClasses] = (int)bp.order.size();
+    bp.task_first[kNumClasses] = ntasks;
+    size_t o2 = 0;
+    bp.off_inst = o2;
+    o2 += align256(sizeof(BatchInst) * (size_t)batch);
+    bp.off_task = o2;
+    o2 += align256(sizeof(BatchTask) * (size_t)ntasks);
+    bp.off_blocks = o2;
+    for (int32_t i = 0; i < batch; ++i) {
+        bp.inst_off[i] = o2;
+        o2 += inst_block_bytes(padded_n(n[i]), bp.slots);
+    }
+    for (int c = 0; c < kNumClasses; ++c) {
+        bp.off_part[c] = o2;
+        o2 += align256(sizeof(double) * (size_t)(bp.task_first[c + 1] - bp.task_first[c]) *
+                       (size_t)pass_partial_elems(kClassNp[c], false));
+    }
+    bp.total = o2;
+    return SCQR_OK;
+}
+
+// Host-to-device upload of the batched descriptors through pinned staging buffers owned by the
+// library (allocated on first use, grown when needed, reused once their last copy completed).
+struct Staging {
+    void *buf = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+std::mutex g_stage_mu;
+Staging g_stage[2];
+int g_stage_next = 0;
+
+hipError_t upload(hipStream_t s, void *dst, const void *src, size_t bytes)
+{
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    Staging &st = g_stage[g_stage_next];
+    g_stage_next ^= 1;
+    hipError_t e = hipSuccess;
+    if (st.done) {
+        e = hipEventSynchronize(st.done);
+        if (e != hipSuccess) return e;
+    } else {
+        e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+    }
+    if (st.cap < bytes) {
+        if (st.buf) (void)hipHostFree(st.buf);
+        st.buf = nullptr;
+        st.cap = 0;
+        e = hipHostMalloc(&st.buf, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        st.cap = bytes;
+    }
+    std::memcpy(st.buf, src, bytes);
+    e = hipMemcpyAsync(dst, st.buf, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(st.done, s);
+}
 
 }  // namespace
 
@@ -347,14 +477,15 @@ scqr_status scqr_batched_workspace_bytes(int32_t batch, const int64_t *m, const 
                                          const scqr_opts *opts, size_t *bytes)
 {
     if (!bytes || batch < 0 || (batch > 0 && (!m || !n))) return SCQR_E_INVALID;
-    size_t mx = 0;
-    for (int32_t i = 0; i < batch; ++i) {
-        size_t b = 0;
-        scqr_status st = scqr_workspace_bytes(m[i], n[i], nullptr, opts, &b);
-        if (st != SCQR_OK) return st;
-        mx = b > mx ? b : mx;
-    }
-    *bytes = mx;
+    scqr_opts o;
+    if (opts)
+        o = *opts;
+    else
+        scqr_default_opts(&o);
+    BatchPlan bp;
+    scqr_status st = plan_batch(batch, m, n, o, bp);
+    if (st != SCQR_OK) return st;
+    *bytes = bp.total;
     return SCQR_OK;
 }
 
@@ -365,16 +496,131 @@ scqr_status scqr_qr_batched(void *stream, int32_t batch, const int64_t *m, const
     if (batch < 0) return SCQR_E_INVALID;
     if (batch == 0) return SCQR_OK;
     if (!m || !n || !X || !Q || !R || !infos || !ws) return SCQR_E_INVALID;
-    size_t need = 0;
-    scqr_status st = scqr_batched_workspace_bytes(batch, m, n, opts, &need);
+    scqr_opts o;
+    if (opts)
+        o = *opts;
+    else
+        scqr_default_opts(&o);
+    if (o.final_gram || o.trace) return SCQR_E_UNSUPPORTED;
+    BatchPlan bp;
+    scqr_status st = plan_batch(batch, m, n, o, bp);
     if (st != SCQR_OK) return st;
-    if (ws_bytes < need) return SCQR_E_WORKSPACE;
+    if (ws_bytes < bp.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return SCQR_E_WORKSPACE;
     for (int32_t i = 0; i < batch; ++i) {
-        st = scqr_qr(stream, m[i], n[i], X[i], n[i], nullptr, Q[i], n[i], R[i], n[i], ws, ws_bytes, opts,
-                     infos + i);
-        if (st != SCQR_OK) return st;
+        if (!X[i] || !Q[i] || !R[i]) return SCQR_E_INVALID;
+        const size_t xb = mat_bytes(m[i], n[i], n[i]), rb = mat_bytes(n[i], n[i], n[i]);
+        if (Q[i] != X[i] && ranges_overlap(X[i], xb, Q[i], xb)) return SCQR_E_INVALID;
+        if (ranges_overlap(R[i], rb, X[i], xb) || ranges_overlap(R[i], rb, Q[i], xb)) return SCQR_E_INVALID;
+        if (ranges_overlap(ws, bp.total, X[i], xb) || ranges_overlap(ws, bp.total, Q[i], xb) ||
+            ranges_overlap(ws, bp.total, R[i], rb))
+            return SCQR_E_INVALID;
     }
-    return SCQR_OK;
+
+    // descriptors (instances in class order, then tasks), uploaded to the head of the workspace
+    char *base = static_cast<char *>(ws);
+    std::vector<unsigned char> host(bp.off_blocks, 0);
+    BatchInst *hi = reinterpret_cast<BatchInst *>(host.data() + bp.off_inst);
+    BatchTask *ht = reinterpret_cast<BatchTask *>(host.data() + bp.off_task);
+    const BatchInst *dinst = reinterpret_cast<const BatchInst *>(base + bp.off_inst);
+    const BatchTask *dtask = reinterpret_cast<const BatchTask *>(base + bp.off_task);
+    BatchClass cls[kNumClasses];
+    for (int c = 0; c < kNumClasses; ++c) {
+        const int np = kClassNp[c];
+        const int64_t elems = pass_partial_elems(np, false);
+        BatchClass &bc = cls[c];
+        bc.np = np;
+        bc.ninst = bp.cls_first[c + 1] - bp.cls_first[c];
+        bc.ntasks = bp.task_first[c + 1] - bp.task_first[c];
+        bc.insts = dinst + bp.cls_first[c];
+        bc.tasks = dtask + bp.task_first[c];
+        bc.partials = reinterpret_cast<double *>(base + bp.off_part[c]);
+        bc.vec = true;
+        int t = 0;
+        for (int k = bp.cls_first[c]; k < bp.cls_first[c + 1]; ++k) {
+            const int i = bp.order[k];
+            BatchInst &I = hi[k];
+            I.p.m = m[i];
+            I.p.n = (int)n[i];
+            I.p.np = np;
+            I.p.X = X[i];
+            I.p.ldx = n[i];
+            I.p.Q = Q[i];
+            I.p.ldq = n[i];
+            I.p.R = R[i];
+            I.p.ldr = n[i];
+            I.p.zero = 0;
+            char *blk = base + bp.inst_off[i];
+            size_t o2 = 0;
+            I.w.ctl = reinterpret_cast<Ctl *>(blk + o2);
+            o2 += align256(sizeof(Ctl));
+            I.w.Rhist = reinterpret_cast<double *>(blk + o2);
+            o2 += align256(sizeof(double) * np * np * bp.slots);
+            I.w.dhist = reinterpret_cast<double *>(blk + o2);
+            o2 += align256(sizeof(double) * np * bp.slots);
+            I.w.gsum = reinterpret_cast<double *>(blk + o2);
+            o2 += align256(sizeof(double) * elems);
+            if (np > 128) {
+                I.w.G = reinterpret_cast<double *>(blk + o2);
+                o2 += align256(sizeof(double) * np * (np + 1));
+                I.w.Racc[0] = reinterpret_cast<double *>(blk + o2);
+                o2 += align256(sizeof(double) * np * np);
+                I.w.Racc[1] = reinterpret_cast<double *>(blk + o2);
+            }
+            I.w.parts_elems = elems;
+            I.info = infos + i;
+            I.t0 = t;
+            for (int q = 0; q < bp.ntask[i]; ++q, ++t) {
+                BatchTask &T = ht[bp.task_first[c] + t];
+                T.inst = k - bp.cls_first[c];
+                T.r0 = (int64_t)q * bp.rows_per_task[c];
+                const int64_t r1 = T.r0 + bp.rows_per_task[c];
+                T.r1 = r1 < m[i] ? r1 : m[i];
+            }
+            I.t1 = t;
+            if ((n[i] & 1) || (reinterpret_cast<uintptr_t>(X[i]) & 15) || (reinterpret_cast<uintptr_t>(Q[i]) & 15))
+                bc.vec = false;
+        }
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = upload(s, base, host.data(), host.size());
+
+    SchedParams sp{};
+    sp.schedule = o.schedule;
+    sp.shift_mode = o.shift_mode;
+    sp.precision = o.precision;
+    sp.max_passes = o.max_passes;
+    sp.final_gram = 0;
+    sp.force_bd = o.debug_force_breakdown_pass;
+    sp.zero_shift = o.debug_zero_shift;
+    sp.oblique = 0;
+    sp.custom_alpha = o.custom_alpha;
+    sp.bnorm_user = 0.0;
+    sp.trace = nullptr;
+    sp.info = nullptr;
+    const bool f32 = o.precision == SCQR_PREC_FP32_FIRST;
+    // one launch per class and step; classes of the same step are independent
+    for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) e = launch_init_b(s, cls[c]);
+    for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
+        e = launch_pass_b(s, cls[c], 0, 0, f32, 0);
+        if (e == hipSuccess) e = launch_reduce_b(s, cls[c], 0, 0);
+        if (e == hipSuccess) e = launch_chol_b(s, cls[c], sp, 1, 0);
+    }
+    if (f32) {
+        for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
+            e = launch_pass_b(s, cls[c], 0, -1, false, 0);
+            if (e == hipSuccess) e = launch_reduce_b(s, cls[c], -1, 0);
+            if (e == hipSuccess) e = launch_chol_b(s, cls[c], sp, 1, 1);
+        }
+    }
+    for (int pass = 1; pass <= bp.P && e == hipSuccess; ++pass) {
+        for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
+            e = launch_pass_b(s, cls[c], 1, pass, false, 0);
+            if (e == hipSuccess) e = launch_reduce_b(s, cls[c], pass, 0);
+            if (e == hipSuccess && pass < bp.P) e = launch_chol_b(s, cls[c], sp, pass + 1, 0);
+        }
+    }
+    for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) e = launch_finalize_b(s, cls[c]);
+    return hip_status(e);
 }
 
 scqr_status scqr_backward_workspace_bytes(int64_t m, int64_t n, size_t *bytes)

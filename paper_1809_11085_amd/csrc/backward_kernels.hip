@@ -21,7 +21,7 @@ struct BwdWork {
 int bwd_grid(int64_t m)
 {
     int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t panels = (m + 15) / 16;
     const int64_t cap = 2 * (int64_t)(cus > 0 ? cus : 256);
     const int64_t g = panels < cap ? panels : cap;
@@ -255,7 +255,7 @@ static hipError_t bwd_impl(hipStream_t s, int64_t m, int n, const double *Q, int
     hipLaunchKernelGGL((k_bwd_small<NP>), dim3(1), dim3(256), 0, s, b, n, R, ldr, dR, lddr, dQ ? 1 : 0);
     prof_after(s);
     int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int64_t blocks = (m + 255) / 256;
     if (blocks > 4 * (int64_t)cus) blocks = 4 * (int64_t)cus;
     if (blocks < 1) blocks = 1;

@@ -374,8 +374,8 @@ __device__ double shift_value(const SchedParams &sp, int64_t m, int n, double no
 // variant 0: pass `pass` of the schedule.  variant 1: binary64 redo of pass 1 after the
 // FP32-first attempt was rejected.
 template <int NP>
-__global__ void __launch_bounds__(kCholThreads)
-k_chol(Problem p, Work w, SchedParams sp, int pass, int variant)
+__device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const SchedParams &sp, int pass,
+                                          int variant)
 {
     constexpr bool IN_LDS = NP <= 128;
     constexpr int S = NP + 1;
@@ -561,8 +561,27 @@ k_chol(Problem p, Work w, SchedParams sp, int pass, int variant)
     }
 }
 
+template <int NP>
+__global__ void __launch_bounds__(kCholThreads)
+k_chol(Problem p, Work w, SchedParams sp, int pass, int variant)
+{
+    chol_body<NP>(p, w, sp, pass, variant);
+}
+
+// Batched form: workgroup i runs the step for instance i (its own info record; no trace).
+template <int NP>
+__global__ void __launch_bounds__(kCholThreads)
+k_chol_b(const BatchInst *__restrict__ insts, SchedParams sp, int pass, int variant)
+{
+    const BatchInst I = load_cview(insts + blockIdx.x);
+    SchedParams spi = sp;
+    spi.info = I.info;
+    spi.trace = nullptr;
+    chol_body<NP>(I.p, I.w, spi, pass, variant);
+}
+
 // Initialise the control block and the caller's info record.
-__global__ void k_init(Ctl *ctl, scqr_info *info, uint32_t *counters, int ncounters)
+__device__ __forceinline__ void init_body(Ctl *ctl, scqr_info *info, uint32_t *counters, int ncounters)
 {
     for (int i = threadIdx.x; i < ncounters; i += blockDim.x) counters[i] = 0u;
     if (threadIdx.x == 0) {
@@ -583,6 +602,17 @@ __global__ void k_init(Ctl *ctl, scqr_info *info, uint32_t *counters, int ncount
             info->bnorm = 1.0;
         }
     }
+}
+
+__global__ void k_init(Ctl *ctl, scqr_info *info, uint32_t *counters, int ncounters)
+{
+    init_body(ctl, info, counters, ncounters);
+}
+
+__global__ void k_init_b(const BatchInst *__restrict__ insts)
+{
+    const BatchInst I = load_cview(insts + blockIdx.x);
+    init_body(I.w.ctl, I.info, nullptr, 0);
 }
 
 // G (caller layout, both triangles) from the level-2 partials, for scqr_gram.
@@ -787,6 +817,16 @@ __global__ void __launch_bounds__(256) k_finalize_r(Problem p, Work w)
         finalize_big<NP>(p, w);
 }
 
+template <int NP>
+__global__ void __launch_bounds__(256) k_finalize_b(const BatchInst *__restrict__ insts)
+{
+    const BatchInst I = load_cview(insts + blockIdx.x);
+    if constexpr (NP <= 64)
+        finalize_small<NP>(I.p, I.w, I.w.ctl->pass);
+    else
+        finalize_big<NP>(I.p, I.w);
+}
+
 // ||G - I||_F of the final Gram (final_gram option).
 template <int NP>
 __global__ void __launch_bounds__(256) k_final_omega(Problem p, Work w, SchedParams sp)
@@ -796,7 +836,6 @@ __global__ void __launch_bounds__(256) k_final_omega(Problem p, Work w, SchedPar
     if (!(ctl->active && ctl->last > 0)) return;
     constexpr int NT = NP / 16;
     constexpr int T = NT * (NT + 1) / 2;
-    const int64_t E = (int64_t)T * 256;
     const int n = p.n;
     double acc = 0.0;
     for (int e = threadIdx.x; e < T * 256; e += blockDim.x) {
@@ -892,6 +931,50 @@ hipError_t launch_final_omega(hipStream_t s, const Problem &p, const Work &w, co
     case 64: hipLaunchKernelGGL((k_final_omega<64>), dim3(1), dim3(256), 0, s, p, w, sp); break;
     case 128: hipLaunchKernelGGL((k_final_omega<128>), dim3(1), dim3(256), 0, s, p, w, sp); break;
     case 256: hipLaunchKernelGGL((k_final_omega<256>), dim3(1), dim3(256), 0, s, p, w, sp); break;
+    default: prof_after(s); return hipErrorInvalidValue;
+    }
+    prof_after(s);
+    return hipGetLastError();
+}
+
+// ---- batched launchers (one workgroup per instance) ----------------------------------------
+hipError_t launch_init_b(hipStream_t s, const BatchClass &c)
+{
+    if (c.ninst <= 0) return hipSuccess;
+    prof_before(s, "b_init");
+    hipLaunchKernelGGL(k_init_b, dim3((unsigned)c.ninst), dim3(256), 0, s, c.insts);
+    prof_after(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_b(hipStream_t s, const BatchClass &c, const SchedParams &sp, int pass, int variant)
+{
+    if (c.ninst <= 0) return hipSuccess;
+    dim3 grid((unsigned)c.ninst), block(kCholThreads);
+    prof_before(s, "b_chol");
+    switch (c.np) {
+    case 16: hipLaunchKernelGGL((k_chol_b<16>), grid, block, 0, s, c.insts, sp, pass, variant); break;
+    case 32: hipLaunchKernelGGL((k_chol_b<32>), grid, block, 0, s, c.insts, sp, pass, variant); break;
+    case 64: hipLaunchKernelGGL((k_chol_b<64>), grid, block, 0, s, c.insts, sp, pass, variant); break;
+    case 128: hipLaunchKernelGGL((k_chol_b<128>), grid, block, 0, s, c.insts, sp, pass, variant); break;
+    case 256: hipLaunchKernelGGL((k_chol_b<256>), grid, block, 0, s, c.insts, sp, pass, variant); break;
+    default: prof_after(s); return hipErrorInvalidValue;
+    }
+    prof_after(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_b(hipStream_t s, const BatchClass &c)
+{
+    if (c.ninst <= 0) return hipSuccess;
+    dim3 grid((unsigned)c.ninst), block(256);
+    prof_before(s, "b_finalize_r");
+    switch (c.np) {
+    case 16: hipLaunchKernelGGL((k_finalize_b<16>), grid, block, 0, s, c.insts); break;
+    case 32: hipLaunchKernelGGL((k_finalize_b<32>), grid, block, 0, s, c.insts); break;
+    case 64: hipLaunchKernelGGL((k_finalize_b<64>), grid, block, 0, s, c.insts); break;
+    case 128: hipLaunchKernelGGL((k_finalize_b<128>), grid, block, 0, s, c.insts); break;
+    case 256: hipLaunchKernelGGL((k_finalize_b<256>), grid, block, 0, s, c.insts); break;
     default: prof_after(s); return hipErrorInvalidValue;
     }
     prof_after(s);

@@ -50,14 +50,17 @@ __device__ __forceinline__ void wave_sync()
 //   F32: Gram in binary32 MFMA, flushed to binary64 after every 64-row chain (MODE 0 only).
 //   VEC: n even, even leading dimensions and 16-byte aligned X, Q (pairs of doubles per access).
 //   PR: rows per panel (32: 8 waves per workgroup, 64: 4 waves).
+//   The workgroup's waves take panels pfirst + wave, + pstride, ... below pend; the
+//   workgroup's partial Gram goes to part_out.
 template <int NP, int MODE, bool F32, bool VEC, int PR>
-__global__ void __launch_bounds__(PR == 64 ? 256 : 512)
-k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
-            const double *__restrict__ dinv, double *__restrict__ partials,
-            const Ctl *__restrict__ ctl, int pass, int final_gram)
+__device__ __forceinline__ void
+pass_tile_body(const Problem &p, double *__restrict__ Qout, const double *__restrict__ Rt,
+               const double *__restrict__ dinv, double *__restrict__ part_out,
+               const Ctl *__restrict__ ctl, int pass, int final_gram, int64_t pfirst,
+               int64_t pstride, int64_t pend)
 {
-    // Qout == p.Q; passing it as a restrict parameter lets the factor loads stay scalar.  When
-    // Q aliases X every row is read before it is written by the same wave.
+    // Qout == p.Q, a restrict parameter so that the factor loads stay scalar.  When Q aliases
+    // X every row is read before it is written by the same wave.
     constexpr int WAVES = PR == 64 ? 4 : 8;
     constexpr int NT = NP / 16;
     constexpr int T = NT * (NT + 1) / 2;
@@ -76,8 +79,8 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
 
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t W = (int64_t)gridDim.x * WAVES;
-    const int64_t npanels = (p.m + PR - 1) / PR;
+    const int64_t W = pstride;
+    const int64_t npanels = pend;
     const int n = p.n;
     double *P = lds + wv * PANEL;
     const int li = lane & 15, lk = lane >> 4;
@@ -92,7 +95,7 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
                 K -= J;
                 ++J;
             }
-            bl[idx] = -Rt[(16 * K + 4 * s4 + (l >> 4)) * NP + 16 * J + (l & 15)];
+            bl[idx] = -as_cview(Rt)[(16 * K + 4 * s4 + (l >> 4)) * NP + 16 * J + (l & 15)];
         }
         __syncthreads();
     }
@@ -116,12 +119,12 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
                 const bool ok = row < p.m && c < n;
                 const int64_t rr = row < p.m ? row : p.m - 1;
                 const int cc = c < n ? c : 0;
-                const double2 v = *reinterpret_cast<const double2 *>(p.X + rr * p.ldx + cc);
-                pre[i] = ok ? v : make_double2(0.0, 0.0);
+                const d2 v = *reinterpret_cast<gview<const d2>>(as_global(p.X) + rr * p.ldx + cc);
+                pre[i] = ok ? make_double2(v.x, v.y) : make_double2(0.0, 0.0);
             } else {
                 double a = 0.0, b = 0.0;
                 if (row < p.m) {
-                    const double *src = p.X + row * p.ldx + c;
+                    const gview<const double> src = as_global(p.X) + row * p.ldx + c;
                     if (c < n) a = src[0];
                     if (c + 1 < n) b = src[1];
                 }
@@ -129,7 +132,7 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
             }
         }
     };
-    int64_t pn = (int64_t)blockIdx.x * WAVES + wv;
+    int64_t pn = pfirst + wv;
     if (pn < npanels) load_panel(pn);
     for (; pn < npanels; pn += W) {
         const int64_t r0 = pn * PR;
@@ -185,8 +188,8 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
                         // re-laundered every two rows: later rows' scalar loads may not be
                         // hoisted above earlier rows' work (they would exhaust the SGPRs)
                         if ((k & 1) == 0) asm volatile("" : "+s"(offk));
-                        const double *Rd = Rt + offk + (16 * J) * NP + 16 * J;
-                        const double qk = t[k] * dinv[offk + 16 * J + k];
+                        const cview<double> Rd = as_cview(Rt) + offk + (16 * J) * NP + 16 * J;
+                        const double qk = t[k] * as_cview(dinv)[offk + 16 * J + k];
                         t[k] = qk;
 #pragma unroll
                         for (int j = k + 1; j < 16; ++j) t[j] = __builtin_fma(-qk, Rd[k * NP + j], t[j]);
@@ -204,9 +207,9 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
                 const int64_t row = r0 + r;
                 if (row < p.m && c < n) {
                     const double2 v = *reinterpret_cast<const double2 *>(P + r * S + c);
-                    double *dst = Qout + row * p.ldq + c;
+                    const gview<double> dst = as_global(Qout) + row * p.ldq + c;
                     if (VEC) {
-                        *reinterpret_cast<double2 *>(dst) = v;
+                        *reinterpret_cast<gview<d2>>(dst) = (d2){v.x, v.y};
                     } else {
                         dst[0] = v.x;
                         if (c + 1 < n) dst[1] = v.y;
@@ -272,8 +275,44 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
         }
         __syncthreads();
     }
-    double *out = partials + (int64_t)blockIdx.x * (T * 256);
-    for (int e = threadIdx.x; e < T * 256; e += WAVES * 64) out[e] = red[e];
+    for (int e = threadIdx.x; e < T * 256; e += WAVES * 64) part_out[e] = red[e];
+}
+
+template <int NP, int MODE, bool F32, bool VEC, int PR>
+__global__ void __launch_bounds__(PR == 64 ? 256 : 512)
+k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
+            const double *__restrict__ dinv, double *__restrict__ partials,
+            const Ctl *__restrict__ ctl, int pass, int final_gram)
+{
+    // Qout == p.Q; passing it as a restrict parameter lets the factor loads stay scalar.
+    constexpr int WAVES = PR == 64 ? 4 : 8;
+    constexpr int NT = NP / 16;
+    constexpr int T = NT * (NT + 1) / 2;
+    pass_tile_body<NP, MODE, F32, VEC, PR>(p, Qout, Rt, dinv, partials + (int64_t)blockIdx.x * (T * 256), ctl,
+                                           pass, final_gram, (int64_t)blockIdx.x * WAVES,
+                                           (int64_t)gridDim.x * WAVES, (p.m + PR - 1) / PR);
+}
+
+// Batched form: workgroup b processes task b (rows [r0, r1) of one instance); pass > 1 reads
+// the instance's Q.
+template <int NP, int MODE, bool F32, bool VEC, int PR>
+__global__ void __launch_bounds__(PR == 64 ? 256 : 512)
+k_pass_tile_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__ tasks,
+              double *__restrict__ partials, int pass, int final_gram)
+{
+    constexpr int WAVES = PR == 64 ? 4 : 8;
+    constexpr int NT = NP / 16;
+    constexpr int T = NT * (NT + 1) / 2;
+    const BatchTask t = load_cview(tasks + blockIdx.x);
+    const BatchInst I = load_cview(insts + t.inst);
+    Problem p = I.p;
+    if (pass > 1) {
+        p.X = p.Q;
+        p.ldx = p.ldq;
+    }
+    pass_tile_body<NP, MODE, F32, VEC, PR>(p, p.Q, factor_of(I.w, NP, pass), dinv_of(I.w, NP, pass),
+                                           partials + (int64_t)blockIdx.x * (T * 256), I.w.ctl, pass,
+                                           final_gram, t.r0 / PR, WAVES, (t.r1 + PR - 1) / PR);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -281,16 +320,15 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
 // x_J, receives -q_k r_kj for every earlier k in increasing order (solved values are re-read
 // from the thread's own output row), then is solved against the diagonal block.
 template <int NP>
-__global__ void __launch_bounds__(256)
-k_trsm_big(Problem p, const double *__restrict__ Rt, const double *__restrict__ dinv,
-           const Ctl *__restrict__ ctl, int pass)
+__device__ __forceinline__ void
+trsm_big_body(const Problem &p, const double *__restrict__ Rt, const double *__restrict__ dinv,
+              const Ctl *__restrict__ ctl, int pass, int64_t row0, int64_t rstride, int64_t rend)
 {
     if (!gate(ctl, pass)) return;
     const int n = p.n;
-    for (int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x; row < p.m;
-         row += (int64_t)gridDim.x * 256) {
-        const double *xr = p.X + row * p.ldx;
-        double *qr = p.Q + row * p.ldq;
+    for (int64_t row = row0 + threadIdx.x; row < rend; row += rstride) {
+        const gview<const double> xr = as_global(p.X) + row * p.ldx;
+        const gview<double> qr = as_global(p.Q) + row * p.ldq;
         for (int J = 0; J < NP / 64; ++J) {
             double t[64];
 #pragma unroll
@@ -299,15 +337,15 @@ k_trsm_big(Problem p, const double *__restrict__ Rt, const double *__restrict__ 
                 for (int kk = 0; kk < 64; ++kk) {
                     const int k = 64 * K + kk;
                     const double qk = (k < n) ? qr[k] : 0.0;
-                    const double *rk = Rt + (int64_t)k * NP + 64 * J;
+                    const cview<double> rk = as_cview(Rt) + (int64_t)k * NP + 64 * J;
 #pragma unroll
                     for (int c = 0; c < 64; ++c) t[c] = __builtin_fma(-qk, rk[c], t[c]);
                 }
             }
-            const double *rd = Rt + (int64_t)(64 * J) * NP + 64 * J;
+            const cview<double> rd = as_cview(Rt) + (int64_t)(64 * J) * NP + 64 * J;
 #pragma unroll
             for (int k = 0; k < 64; ++k) {
-                const double qk = t[k] * dinv[64 * J + k];
+                const double qk = t[k] * as_cview(dinv)[64 * J + k];
                 t[k] = qk;
 #pragma unroll
                 for (int j = k + 1; j < 64; ++j) t[j] = __builtin_fma(-qk, rd[k * NP + j], t[j]);
@@ -319,6 +357,28 @@ k_trsm_big(Problem p, const double *__restrict__ Rt, const double *__restrict__ 
     }
 }
 
+template <int NP>
+__global__ void __launch_bounds__(256)
+k_trsm_big(Problem p, const double *__restrict__ Rt, const double *__restrict__ dinv,
+           const Ctl *__restrict__ ctl, int pass)
+{
+    trsm_big_body<NP>(p, Rt, dinv, ctl, pass, (int64_t)blockIdx.x * 256, (int64_t)gridDim.x * 256, p.m);
+}
+
+template <int NP>
+__global__ void __launch_bounds__(256)
+k_trsm_big_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__ tasks, int pass)
+{
+    const BatchTask t = load_cview(tasks + blockIdx.x);
+    const BatchInst I = load_cview(insts + t.inst);
+    Problem p = I.p;
+    if (pass > 1) {
+        p.X = p.Q;
+        p.ldx = p.ldq;
+    }
+    trsm_big_body<NP>(p, factor_of(I.w, NP, pass), dinv_of(I.w, NP, pass), I.w.ctl, pass, t.r0, 256, t.r1);
+}
+
 // ------------------------------------------------------------------------------------------
 // LDS-staged Gram for any NP (used for n > 64 and for the oblique inner product).  A workgroup
 // of WAVES waves streams 16-row panels through LDS; wave w owns the upper tiles t with
@@ -328,10 +388,12 @@ k_trsm_big(Problem p, const double *__restrict__ Rt, const double *__restrict__ 
 //   EUC: with OBL, also the Euclidean X^T X (second half of the partial) and the per-workgroup
 //        Gershgorin maximum of B (first-pass shift of equation (eq:finds2B)).
 //   F32: binary32 MFMA, flushed to binary64 after every 64 rows.
+//   The workgroup takes the 16-row panels [p0, p1) and writes its partial to part_out (and its
+//   Gershgorin maximum to *bmax_out).
 template <int NP, int WAVES, bool OBL, bool EUC, bool F32>
-__global__ void __launch_bounds__(WAVES * 64)
-k_gram_lds(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
-           const Ctl *__restrict__ ctl, int pass, int final_gram)
+__device__ __forceinline__ void
+gram_lds_body(const Problem &p, double *__restrict__ part_out, double *__restrict__ bmax_out,
+              const Ctl *__restrict__ ctl, int pass, int final_gram, int64_t p0, int64_t p1)
 {
     constexpr int NT = NP / 16;
     constexpr int T = NT * (NT + 1) / 2;
@@ -349,11 +411,6 @@ k_gram_lds(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
     const int nthr = WAVES * 64;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int n = p.n;
-    const int64_t npanels = (p.m + PR - 1) / PR;
-    // contiguous share of panels per workgroup
-    const int64_t per = (npanels + gridDim.x - 1) / gridDim.x;
-    const int64_t p0 = (int64_t)blockIdx.x * per;
-    const int64_t p1 = (p0 + per < npanels) ? p0 + per : npanels;
 
     d4 acc[TPW], acce[EUC ? TPW : 1];
     f4 a32[F32 ? TPW : 1];
@@ -377,7 +434,7 @@ k_gram_lds(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
             const int rr = idx / NP, c = idx % NP;
             const int64_t row = r0 + rr - HALO;
             double v = 0.0;
-            if (row >= 0 && row < p.m && c < n) v = p.X[row * p.ldx + c];
+            if (row >= 0 && row < p.m && c < n) v = as_global(p.X)[row * p.ldx + c];
             xs[rr * S + c] = v;
         }
         if (OBL) {
@@ -385,9 +442,9 @@ k_gram_lds(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
                 const int64_t row = r0 + rr;
                 double lo = 0.0, d = 0.0, up = 0.0;
                 if (row < p.m) {
-                    d = p.bdiag[row];
-                    if (row > 0) lo = p.boff[row - 1];
-                    if (row + 1 < p.m) up = p.boff[row];
+                    d = as_global(p.bdiag)[row];
+                    if (row > 0) lo = as_global(p.boff)[row - 1];
+                    if (row + 1 < p.m) up = as_global(p.boff)[row];
                     if (EUC) {
                         double g = (row > 0 ? fabs(lo) : 0.0) + fabs(d);
                         if (row + 1 < p.m) g = g + fabs(up);
@@ -447,7 +504,7 @@ k_gram_lds(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
         }
     }
     const int64_t E = (int64_t)T * 256;
-    double *out = partials + (int64_t)blockIdx.x * (EUC ? 2 * E : E);
+    double *out = part_out;
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
         const int t = wv + u * WAVES;
@@ -465,9 +522,44 @@ k_gram_lds(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
         if (threadIdx.x == 0) {
             double g = 0.0;
             for (int i = 0; i < nthr; ++i) g = gmax[i] > g ? gmax[i] : g;
-            bmax[blockIdx.x] = g;
+            *bmax_out = g;
         }
     }
+}
+
+template <int NP, int WAVES, bool OBL, bool EUC, bool F32>
+__global__ void __launch_bounds__(WAVES * 64)
+k_gram_lds(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
+           const Ctl *__restrict__ ctl, int pass, int final_gram)
+{
+    constexpr int NT = NP / 16;
+    constexpr int64_t E = (int64_t)NT * (NT + 1) / 2 * 256;
+    const int64_t npanels = (p.m + 15) / 16;
+    // contiguous share of 16-row panels per workgroup
+    const int64_t per = (npanels + gridDim.x - 1) / gridDim.x;
+    const int64_t p0 = (int64_t)blockIdx.x * per;
+    const int64_t p1 = (p0 + per < npanels) ? p0 + per : npanels;
+    gram_lds_body<NP, WAVES, OBL, EUC, F32>(p, partials + (int64_t)blockIdx.x * (EUC ? 2 * E : E),
+                                            bmax + blockIdx.x, ctl, pass, final_gram, p0, p1);
+}
+
+// Batched form (Euclidean): workgroup b takes the rows of task b; pass > 1 reads the Q.
+template <int NP, int WAVES, bool F32>
+__global__ void __launch_bounds__(WAVES * 64)
+k_gram_lds_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__ tasks,
+             double *__restrict__ partials, int pass, int final_gram)
+{
+    constexpr int NT = NP / 16;
+    constexpr int64_t E = (int64_t)NT * (NT + 1) / 2 * 256;
+    const BatchTask t = load_cview(tasks + blockIdx.x);
+    const BatchInst I = load_cview(insts + t.inst);
+    Problem p = I.p;
+    if (pass >= 1) {  // the Gram of pass >= 1 reads the Q its substitution just wrote
+        p.X = p.Q;
+        p.ldx = p.ldq;
+    }
+    gram_lds_body<NP, WAVES, false, false, F32>(p, partials + (int64_t)blockIdx.x * E, nullptr, I.w.ctl, pass,
+                                                final_gram, t.r0 / 16, (t.r1 + 15) / 16);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -517,6 +609,32 @@ k_reduce(const double *__restrict__ partials, double *__restrict__ lvl2, double 
         gsum[e] = s;
     }
     if (threadIdx.x == 0) counters[blockIdx.x] = 0u;
+}
+
+// Batched reduction: block (x, i) adds the partials of instance i's tasks t0 .. t1-1 in
+// increasing order for its 256 elements (an instance has few tasks, so one level suffices).
+__global__ void __launch_bounds__(256)
+k_reduce_b(const BatchInst *__restrict__ insts, const double *__restrict__ partials, int64_t elems,
+           int pass, int final_gram)
+{
+    const BatchInst I = load_cview(insts + blockIdx.y);
+    const Ctl *ctl = I.w.ctl;
+    if (!gate(ctl, pass)) return;
+    if (!gram_needed(ctl, pass, final_gram)) return;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= elems) return;
+    const int t1 = I.t1;
+    double s = 0.0;
+    int q = I.t0;
+    for (; q + 8 <= t1; q += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = partials[(int64_t)(q + u) * elems + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; q < t1; ++q) s += partials[(int64_t)q * elems + e];
+    I.w.gsum[e] = s;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -697,6 +815,83 @@ hipError_t launch_reduce(hipStream_t s, const Work &w, int pass, int64_t elems, 
     prof_before(s, "reduce");
     hipLaunchKernelGGL(k_reduce, grid, block, 0, s, w.partials, w.lvl2, w.gsum, w.counters, w.nwg,
                        w.nlvl2, elems, w.ctl, pass, final_gram);
+    prof_after(s);
+    return hipGetLastError();
+}
+
+// ---- batched launchers -------------------------------------------------------------------
+template <int NP, bool VEC>
+static void launch_small_b(hipStream_t s, const BatchClass &c, int mode, int pass, bool f32, int final_gram)
+{
+    constexpr int PR = kPanelRows;
+    dim3 grid((unsigned)c.ntasks), block(PR == 64 ? 256 : 512);
+    if (mode == 0 && f32)
+        hipLaunchKernelGGL((k_pass_tile_b<NP, 0, true, VEC, PR>), grid, block, 0, s, c.insts, c.tasks, c.partials,
+                           pass, final_gram);
+    else if (mode == 0)
+        hipLaunchKernelGGL((k_pass_tile_b<NP, 0, false, VEC, PR>), grid, block, 0, s, c.insts, c.tasks, c.partials,
+                           pass, final_gram);
+    else
+        hipLaunchKernelGGL((k_pass_tile_b<NP, 1, false, VEC, PR>), grid, block, 0, s, c.insts, c.tasks, c.partials,
+                           pass, final_gram);
+}
+
+template <int NP>
+static void launch_small_bv(hipStream_t s, const BatchClass &c, int mode, int pass, bool f32, int final_gram)
+{
+    if (c.vec)
+        launch_small_b<NP, true>(s, c, mode, pass, f32, final_gram);
+    else
+        launch_small_b<NP, false>(s, c, mode, pass, f32, final_gram);
+}
+
+template <int NP, int WAVES>
+static void launch_big_b(hipStream_t s, const BatchClass &c, int mode, int pass, bool f32, int final_gram)
+{
+    dim3 grid((unsigned)c.ntasks);
+    if (mode >= 1) {
+        prof_before(s, "b_trsm");
+        hipLaunchKernelGGL((k_trsm_big_b<NP>), grid, dim3(256), 0, s, c.insts, c.tasks, pass);
+        prof_after(s);
+    }
+    prof_before(s, f32 ? "b_gram_f32" : "b_gram");
+    if (f32)
+        hipLaunchKernelGGL((k_gram_lds_b<NP, WAVES, true>), grid, dim3(WAVES * 64), 0, s, c.insts, c.tasks,
+                           c.partials, pass, final_gram);
+    else
+        hipLaunchKernelGGL((k_gram_lds_b<NP, WAVES, false>), grid, dim3(WAVES * 64), 0, s, c.insts, c.tasks,
+                           c.partials, pass, final_gram);
+    prof_after(s);
+}
+
+hipError_t launch_pass_b(hipStream_t s, const BatchClass &c, int mode, int pass, bool fp32_gram, int final_gram)
+{
+    if (c.ntasks <= 0) return hipSuccess;
+    if (c.np <= 64) {
+        prof_before(s, mode == 0 ? (fp32_gram ? "b_gram_f32" : "b_gram") : "b_trsm_gram");
+        switch (c.np) {
+        case 16: launch_small_bv<16>(s, c, mode, pass, fp32_gram, final_gram); break;
+        case 32: launch_small_bv<32>(s, c, mode, pass, fp32_gram, final_gram); break;
+        case 64: launch_small_bv<64>(s, c, mode, pass, fp32_gram, final_gram); break;
+        }
+        prof_after(s);
+        return hipGetLastError();
+    }
+    switch (c.np) {
+    case 128: launch_big_b<128, 4>(s, c, mode, pass, fp32_gram, final_gram); break;
+    case 256: launch_big_b<256, 8>(s, c, mode, pass, fp32_gram, final_gram); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_b(hipStream_t s, const BatchClass &c, int pass, int final_gram)
+{
+    if (c.ninst <= 0) return hipSuccess;
+    const int64_t elems = pass_partial_elems(c.np, false);
+    dim3 grid((unsigned)((elems + 255) / 256), (unsigned)c.ninst), block(256);
+    prof_before(s, "b_reduce");
+    hipLaunchKernelGGL(k_reduce_b, grid, block, 0, s, c.insts, c.partials, elems, pass, final_gram);
     prof_after(s);
     return hipGetLastError();
 }

@@ -13,6 +13,7 @@ constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
 constexpr int kF32Chain = 64;                     // rows per binary32 accumulation chain
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Number of 16 x 16 tiles in the upper triangle of an NP x NP matrix (NP = 16 * NT).
@@ -101,11 +102,11 @@ struct Work {
 };
 
 // Factor and reciprocal diagonal used by the substitution of pass `pass` (slot 0 for pass 0).
-inline const double *factor_of(const Work &w, int np, int pass)
+__host__ __device__ inline const double *factor_of(const Work &w, int np, int pass)
 {
     return w.Rhist + (int64_t)(pass > 1 ? pass - 1 : 0) * np * np;
 }
-inline const double *dinv_of(const Work &w, int np, int pass)
+__host__ __device__ inline const double *dinv_of(const Work &w, int np, int pass)
 {
     return w.dhist + (int64_t)(pass > 1 ? pass - 1 : 0) * np;
 }
@@ -119,6 +120,75 @@ struct SchedParams {
     double *trace;
     scqr_info *info;
 };
+
+// Read-only views in the constant address space.  The triangular factors, their reciprocal
+// diagonals and the batched descriptors are never written while a kernel that reads them runs;
+// loads through such a view of a wave-uniform address are scalar loads, also when the pointer
+// came from memory (a batched descriptor) rather than from a restrict kernel argument.
+template <class T>
+using cview = const __attribute__((address_space(4))) T *;
+template <class T>
+__device__ __forceinline__ cview<T> as_cview(const T *p)
+{
+    return (cview<T>)p;
+}
+// Global-address-space views of caller matrices: pointers taken from a descriptor in memory
+// would otherwise be accessed with flat instructions.
+template <class T>
+using gview = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gview<T> as_global(T *p)
+{
+    return (gview<T>)p;
+}
+// A trivially copyable descriptor loaded as 8-byte words through a constant view.
+template <class T>
+__device__ __forceinline__ T load_cview(const T *p)
+{
+    static_assert(sizeof(T) % 8 == 0, "descriptor size must be a multiple of 8 bytes");
+    constexpr int W = (int)(sizeof(T) / 8);
+    const cview<unsigned long long> src = as_cview(reinterpret_cast<const unsigned long long *>(p));
+    unsigned long long w[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) w[i] = src[i];
+    T v;
+    __builtin_memcpy(&v, w, sizeof(T));
+    return v;
+}
+
+// ---- batched factorization: instances grouped into classes of equal padded width np ----
+// One instance (entry of a device-resident array).  p.X / p.Q / p.R / p.m / p.n are the
+// instance's; w holds its control block, factors, reciprocal diagonals and reduced Gram.
+struct BatchInst {
+    Problem p;
+    Work w;
+    scqr_info *info;
+    int32_t t0, t1;     // its tasks, which are also its partial-Gram slots, in the class
+    int32_t pad[2];
+};
+// Rows [r0, r1) of one instance, processed by one workgroup of a pass kernel; r0 is a
+// multiple of kBatchRowAlign.
+struct BatchTask {
+    int32_t inst;
+    int32_t pad;
+    int64_t r0, r1;
+};
+constexpr int kBatchRowAlign = 32;
+struct BatchClass {
+    int np;
+    int ninst, ntasks;
+    const BatchInst *insts;   // device
+    const BatchTask *tasks;   // device
+    double *partials;         // ntasks x pass_partial_elems(np, false)
+    bool vec;                 // every instance allows 16-byte accesses of X and Q
+};
+hipError_t launch_init_b(hipStream_t s, const BatchClass &c);
+hipError_t launch_pass_b(hipStream_t s, const BatchClass &c, int mode, int pass, bool fp32_gram,
+                         int final_gram);
+hipError_t launch_reduce_b(hipStream_t s, const BatchClass &c, int pass, int final_gram);
+hipError_t launch_chol_b(hipStream_t s, const BatchClass &c, const SchedParams &sp, int pass,
+                         int variant);
+hipError_t launch_finalize_b(hipStream_t s, const BatchClass &c);
 
 // ---- launchers (each enqueues on `stream`, returns hipSuccess or the launch error) ----
 int pass_grid(int64_t m, int np);

@@ -163,3 +163,4 @@ def upstream_grads(m: int, n: int, seed: int):
     dq = np.random.Generator(np.random.PCG64(a)).standard_normal((m, n))
     dr = np.triu(np.random.Generator(np.random.PCG64(b)).standard_normal((n, n)))
     return dq, dr
+

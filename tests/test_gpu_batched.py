@@ -1,0 +1,132 @@
+"""GPU parity of the batched factorization (one launch per width class and step) against the
+oracle and against the single-instance path, through the C ABI.
+
+* Every instance of an uneven batch meets the invariants of the paper (||Q^T Q - I||_2 and
+  ||X - QR||_F / ||X||_F <= 1e-13, R upper triangular with positive diagonal), takes the same
+  number of passes as the oracle for kappa <= 1e12 (nearer 1/u a borderline breakdown may go
+  either way), and for kappa <= 1e6 its factors match the oracle's.
+* Batched and single-instance calls run the same kernels on different row partitions, so they
+  agree to rounding (not bitwise); two batched calls agree bitwise.
+* The schedule is predicated per instance: a non-finite or rank-deficient instance reports its
+  own status while the others complete.
+"""
+import numpy as np
+import pytest
+import torch
+
+import accuracy
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+# (m, n, kappa): every width class, ragged m, n = 1, tall-thin and nearly square instances
+BATCH = [(20000, 16, 1e12), (3000, 1, 1.0), (4097, 17, 1e5), (12345, 32, 1e14), (700, 40, 1e3),
+         (33000, 64, 1e15), (65, 64, 1e6), (5000, 100, 1e9), (9000, 128, 1e13), (1500, 200, 1e4),
+         (2049, 256, 1e6), (40000, 8, 1e8), (257, 255, 1e2), (18000, 48, 1e11), (1024, 128, 1e6),
+         (100000, 16, 1e6)]
+
+
+@pytest.fixture(scope="module")
+def scqr():
+    import paper_1809_11085_amd as s
+    assert torch.cuda.is_available()
+    s.lib()
+    return s
+
+
+@pytest.fixture(scope="module")
+def batch_inputs():
+    return [synth.randsvd(m, n, k, seed=synth.seed_for(4, i)) for i, (m, n, k) in enumerate(BATCH)]
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def test_batched_matches_oracle(scqr, batch_inputs):
+    Xs = [torch.from_numpy(X).cuda() for X in batch_inputs]
+    Qs, Rs, infos = scqr.qr_batched(Xs, schedule="adaptive")
+    for i, ((m, n, kappa), X) in enumerate(zip(BATCH, batch_inputs)):
+        info = infos[i]
+        assert info.status == scqr.OK, (i, info)
+        Qh, Rh = host(Qs[i]), host(Rs[i])
+        assert accuracy.orthogonality(Qh)[0] <= 1e-13, i
+        assert accuracy.residual(X, Qh, Rh) <= 1e-13, i
+        assert np.all(np.diag(Rh) > 0) and np.all(np.tril(Rh, -1) == 0), i
+        ro = oracle.scqr(X, schedule=oracle.ADAPTIVE)
+        if kappa <= 1e12:  # near 1/u a borderline breakdown may go either way (pass count unpinned)
+            assert ro.passes == info.passes and ro.shifted_mask == info.shifted_mask, (i, ro.passes, info.passes)
+        if kappa <= 1e6:
+            assert np.linalg.norm(Rh - ro.R) <= 1e-10 * np.linalg.norm(ro.R), i
+            assert np.max(np.abs(Qh - ro.Q)) <= 1e-10, i
+
+
+def test_batched_vs_single_and_deterministic(scqr, batch_inputs):
+    Xs = [torch.from_numpy(X).cuda() for X in batch_inputs]
+    Q1, R1, i1 = scqr.qr_batched(Xs)
+    Q2, R2, i2 = scqr.qr_batched(Xs)
+    for i in range(len(Xs)):
+        assert torch.equal(Q1[i], Q2[i]) and torch.equal(R1[i], R2[i])
+        Qs, Rs, info = scqr.qr(Xs[i])
+        kappa = BATCH[i][2]
+        if kappa <= 1e12:
+            assert info.passes == i1[i].passes and info.shifted_mask == i1[i].shifted_mask
+        assert abs(info.shift[0] - i1[i].shift[0]) <= 1e-12 * max(info.shift[0], 1e-300)
+        tol = max(1e-13, 64 * 2.0 ** -53 * kappa)
+        assert torch.linalg.norm(R1[i] - Rs) <= tol * torch.linalg.norm(Rs), i
+
+
+def test_batched_in_place_and_fixed3(scqr, batch_inputs):
+    # instances with sqrt(alpha) kappa < u^{-1/2}, where Algorithm 3 alone completes
+    Xs = [torch.from_numpy(batch_inputs[i]).cuda() for i in (0, 1, 2, 4, 6, 7)]
+    ref_Q, ref_R, _ = scqr.qr_batched(Xs, schedule="fixed3")
+    Xc = [X.clone() for X in Xs]
+    Q, R, infos = scqr.qr_batched(Xc, inplace=True, schedule="fixed3")
+    for i in range(len(Xs)):
+        assert Q[i].data_ptr() == Xc[i].data_ptr()
+        assert torch.equal(Q[i], ref_Q[i]) and torch.equal(R[i], ref_R[i])
+        assert infos[i].status == scqr.OK and infos[i].passes == 3
+
+
+def test_batched_per_instance_status(scqr):
+    good = synth.randsvd(5000, 24, 1e8, seed=71)
+    nan = synth.randsvd(3000, 24, 1e3, seed=72)
+    nan[17, 5] = np.nan
+    zero = np.zeros((2000, 33))
+    big = synth.randsvd(8000, 70, 1e10, seed=73)
+    Xs = [torch.from_numpy(a).cuda() for a in (good, nan, zero, big)]
+    Qs, Rs, infos = scqr.qr_batched(Xs)
+    assert infos[0].status == scqr.OK and infos[3].status == scqr.OK
+    assert infos[1].status == scqr.E_NONFINITE
+    assert infos[2].status == scqr.E_BREAKDOWN
+    for i, X in ((0, good), (3, big)):
+        assert accuracy.orthogonality(host(Qs[i]))[0] <= 1e-13
+        assert accuracy.residual(X, host(Qs[i]), host(Rs[i])) <= 1e-13
+
+
+def test_batched_fp32_first(scqr, batch_inputs):
+    sel = [0, 2, 4, 6, 11, 15]
+    Xs = [torch.from_numpy(batch_inputs[i]).cuda() for i in sel]
+    Qs, Rs, infos = scqr.qr_batched(Xs, precision="fp32_first")
+    for k, i in enumerate(sel):
+        X = batch_inputs[i]
+        info = infos[k]
+        assert info.status == scqr.OK, (i, info)
+        ro = oracle.scqr(X, schedule=oracle.ADAPTIVE, precision=1, f32_chain=64)
+        assert info.fell_back_fp64 == ro.fell_back, i
+        assert accuracy.orthogonality(host(Qs[k]))[0] <= 1e-13, i
+        assert accuracy.residual(X, host(Qs[k]), host(Rs[k])) <= 1e-13, i
+        Qs1, Rs1, info1 = scqr.qr(Xs[k], precision="fp32_first")
+        assert info1.fell_back_fp64 == info.fell_back_fp64
+        if BATCH[i][2] <= 1e10:
+            assert info1.passes == info.passes == ro.passes, i
+
+
+def test_batched_argument_errors(scqr):
+    X = torch.zeros((100, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(Exception):
+        scqr.qr_batched([X], final_gram=True)
+    with pytest.raises(Exception):
+        scqr.qr_batched([torch.zeros((4, 8), dtype=torch.float64, device="cuda")])
