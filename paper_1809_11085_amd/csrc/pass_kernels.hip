@@ -38,8 +38,8 @@ __device__ __forceinline__ void wave_sync()
 // Fused pass for n <= 64.  Each wave owns panels of PR rows staged in a per-wave LDS buffer
 // (coalesced 16-byte global loads and stores).  Q = X R~^{-1} is a blocked row-wise
 // substitution over 16-column blocks J:
-//   T_J = X_J - sum_{K<J} Q_K R~_KJ   on FP64 MFMA, with -R~_KJ held in registers for the whole
-//                                     kernel in the 4x16 B-operand layout;
+//   T_J = X_J - sum_{K<J} Q_K R~_KJ   on FP64 MFMA, with -R~_KJ staged once per workgroup in
+//                                     LDS in the 4x16 B-operand layout;
 //   Q_J = T_J R~_JJ^{-1}              one row per lane, forward substitution against the 16x16
 //                                     diagonal block (wave-uniform scalar loads), multiplying by
 //                                     the reciprocal diagonal.
@@ -50,15 +50,35 @@ __device__ __forceinline__ void wave_sync()
 //   F32: Gram in binary32 MFMA, flushed to binary64 after every 64-row chain (MODE 0 only).
 //   VEC: n even, even leading dimensions and 16-byte aligned X, Q (pairs of doubles per access).
 //   PR: rows per panel (32: 8 waves per workgroup, 64: 4 waves).
-//   The workgroup's waves take panels pfirst + wave, + pstride, ... below pend; the
-//   workgroup's partial Gram goes to part_out.
-template <int NP, int MODE, bool F32, bool VEC, int PR>
-__device__ __forceinline__ void
-pass_tile_body(const Problem &p, double *__restrict__ Qout, const double *__restrict__ Rt,
-               const double *__restrict__ dinv, double *__restrict__ part_out,
-               const Ctl *__restrict__ ctl, int pass, int final_gram, int64_t pfirst,
-               int64_t pstride, int64_t pend)
+//   BATCH false: one problem; the waves of all workgroups interleave over its panels.
+//   BATCH true: workgroup b takes task b of the device task table (a row range of one
+//   instance); the problem, factor and control block come from the instance's descriptor.
+//   Workgroup b's partial Gram goes to partials + b * T * 256.
+template <int NP, int MODE, bool F32, bool VEC, int PR, bool BATCH>
+__global__ void __launch_bounds__(PR == 64 ? 256 : 512)
+k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
+            const double *__restrict__ dinv, double *__restrict__ partials,
+            const Ctl *__restrict__ ctl, int pass, int final_gram,
+            const BatchInst *__restrict__ insts, const BatchTask *__restrict__ tasks)
 {
+    int64_t pfirst = 0, pend = 0;
+    if constexpr (BATCH) {
+        // batched: workgroup b processes task b (rows [r0, r1) of one instance); pass > 1
+        // reads the instance's Q
+        const BatchTask tk = load_cview(tasks + blockIdx.x);
+        const BatchInst I = load_cview(insts + tk.inst);
+        p = I.p;
+        if (pass > 1) {
+            p.X = p.Q;
+            p.ldx = p.ldq;
+        }
+        Qout = p.Q;
+        Rt = factor_of(I.w, NP, pass);
+        dinv = dinv_of(I.w, NP, pass);
+        ctl = I.w.ctl;
+        pfirst = tk.r0 / PR;
+        pend = (tk.r1 + PR - 1) / PR;
+    }
     // Qout == p.Q, a restrict parameter so that the factor loads stay scalar.  When Q aliases
     // X every row is read before it is written by the same wave.
     constexpr int WAVES = PR == 64 ? 4 : 8;
@@ -79,8 +99,9 @@ pass_tile_body(const Problem &p, double *__restrict__ Qout, const double *__rest
 
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t W = pstride;
-    const int64_t npanels = pend;
+    // single problem: waves interleaved over all panels; batched: the task's panel range
+    const int64_t W = BATCH ? (int64_t)WAVES : (int64_t)gridDim.x * WAVES;
+    const int64_t npanels = BATCH ? pend : (p.m + PR - 1) / PR;
     const int n = p.n;
     double *P = lds + wv * PANEL;
     const int li = lane & 15, lk = lane >> 4;
@@ -95,7 +116,8 @@ pass_tile_body(const Problem &p, double *__restrict__ Qout, const double *__rest
                 K -= J;
                 ++J;
             }
-            bl[idx] = -as_cview(Rt)[(16 * K + 4 * s4 + (l >> 4)) * NP + 16 * J + (l & 15)];
+            bl[idx] = -(BATCH ? as_cview(Rt)[(16 * K + 4 * s4 + (l >> 4)) * NP + 16 * J + (l & 15)]
+                              : Rt[(16 * K + 4 * s4 + (l >> 4)) * NP + 16 * J + (l & 15)]);
         }
         __syncthreads();
     }
@@ -119,12 +141,18 @@ pass_tile_body(const Problem &p, double *__restrict__ Qout, const double *__rest
                 const bool ok = row < p.m && c < n;
                 const int64_t rr = row < p.m ? row : p.m - 1;
                 const int cc = c < n ? c : 0;
-                const d2 v = *reinterpret_cast<gview<const d2>>(as_global(p.X) + rr * p.ldx + cc);
-                pre[i] = ok ? make_double2(v.x, v.y) : make_double2(0.0, 0.0);
+                double2 v;
+                if constexpr (BATCH) {
+                    const d2 g = *reinterpret_cast<gview<const d2>>(as_global(p.X) + rr * p.ldx + cc);
+                    v = make_double2(g.x, g.y);
+                } else {
+                    v = *reinterpret_cast<const double2 *>(p.X + rr * p.ldx + cc);
+                }
+                pre[i] = ok ? v : make_double2(0.0, 0.0);
             } else {
                 double a = 0.0, b = 0.0;
                 if (row < p.m) {
-                    const gview<const double> src = as_global(p.X) + row * p.ldx + c;
+                    const double *src = p.X + row * p.ldx + c;
                     if (c < n) a = src[0];
                     if (c + 1 < n) b = src[1];
                 }
@@ -132,7 +160,7 @@ pass_tile_body(const Problem &p, double *__restrict__ Qout, const double *__rest
             }
         }
     };
-    int64_t pn = pfirst + wv;
+    int64_t pn = (BATCH ? pfirst : (int64_t)blockIdx.x * WAVES) + wv;
     if (pn < npanels) load_panel(pn);
     for (; pn < npanels; pn += W) {
         const int64_t r0 = pn * PR;
@@ -188,11 +216,19 @@ pass_tile_body(const Problem &p, double *__restrict__ Qout, const double *__rest
                         // re-laundered every two rows: later rows' scalar loads may not be
                         // hoisted above earlier rows' work (they would exhaust the SGPRs)
                         if ((k & 1) == 0) asm volatile("" : "+s"(offk));
-                        const cview<double> Rd = as_cview(Rt) + offk + (16 * J) * NP + 16 * J;
-                        const double qk = t[k] * as_cview(dinv)[offk + 16 * J + k];
-                        t[k] = qk;
+                        if constexpr (BATCH) {
+                            const cview<double> Rd = as_cview(Rt) + offk + (16 * J) * NP + 16 * J;
+                            const double qk = t[k] * as_cview(dinv)[offk + 16 * J + k];
+                            t[k] = qk;
 #pragma unroll
-                        for (int j = k + 1; j < 16; ++j) t[j] = __builtin_fma(-qk, Rd[k * NP + j], t[j]);
+                            for (int j = k + 1; j < 16; ++j) t[j] = __builtin_fma(-qk, Rd[k * NP + j], t[j]);
+                        } else {
+                            const double *Rd = Rt + offk + (16 * J) * NP + 16 * J;
+                            const double qk = t[k] * dinv[offk + 16 * J + k];
+                            t[k] = qk;
+#pragma unroll
+                            for (int j = k + 1; j < 16; ++j) t[j] = __builtin_fma(-qk, Rd[k * NP + j], t[j]);
+                        }
                     }
 #pragma unroll
                     for (int c = 0; c < 16; c += 2) *reinterpret_cast<double2 *>(mr + c) = make_double2(t[c], t[c + 1]);
@@ -207,9 +243,12 @@ pass_tile_body(const Problem &p, double *__restrict__ Qout, const double *__rest
                 const int64_t row = r0 + r;
                 if (row < p.m && c < n) {
                     const double2 v = *reinterpret_cast<const double2 *>(P + r * S + c);
-                    const gview<double> dst = as_global(Qout) + row * p.ldq + c;
+                    double *dst = Qout + row * p.ldq + c;
                     if (VEC) {
-                        *reinterpret_cast<gview<d2>>(dst) = (d2){v.x, v.y};
+                        if constexpr (BATCH)
+                            *reinterpret_cast<gview<d2>>(as_global(dst)) = (d2){v.x, v.y};
+                        else
+                            *reinterpret_cast<double2 *>(dst) = v;
                     } else {
                         dst[0] = v.x;
                         if (c + 1 < n) dst[1] = v.y;
@@ -275,34 +314,232 @@ pass_tile_body(const Problem &p, double *__restrict__ Qout, const double *__rest
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < T * 256; e += WAVES * 64) part_out[e] = red[e];
+    double *out = partials + (int64_t)blockIdx.x * (T * 256);
+    for (int e = threadIdx.x; e < T * 256; e += WAVES * 64) out[e] = red[e];
 }
 
-template <int NP, int MODE, bool F32, bool VEC, int PR>
-__global__ void __launch_bounds__(PR == 64 ? 256 : 512)
-k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
+// ------------------------------------------------------------------------------------------
+// Fused pass for 64 < n <= 128 (NP = 128).  A workgroup of 4 waves shares one 64-row panel in
+// LDS.  Each wave solves its own 16 rows by the same blocked row-wise substitution as the
+// n <= 64 kernel (off-diagonal 16x16 blocks on FP64 MFMA against -R~_KJ held in LDS in the
+// B-operand layout, diagonal blocks one row per lane with wave-uniform scalar loads), the solved
+// panel is written to Q, and wave w accumulates the upper Gram tiles t = w, w+4, ... over all
+// 64 rows.  The next panel's loads are issued before the current one is solved.
+//   MODE 1: substitution + Gram.  MODE 2: substitution only.
+//   The workgroup takes the 64-row panels [p0, p1).
+// Upper Gram tiles t = W, W + WAVES, ... of a PR-row panel (src = panel + (lane/16) S + lane%16),
+// with the tile coordinates known at compile time.
+template <int NP, int W, int WAVES, int TPW, int PR, int S>
+__device__ __forceinline__ void wide_gram(d4 (&acc)[TPW], const double *src)
+{
+    constexpr int NT = NP / 16;
+    constexpr int T = NT * (NT + 1) / 2;
+    for (int s4 = 0; s4 < PR / 4; ++s4) {
+        const double *row = src + 4 * s4 * S;
+        double op[NT];
+#pragma unroll
+        for (int b = 0; b < NT; ++b) op[b] = row[16 * b];
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            const int t = W + u * WAVES;
+            if (t < T) {
+                int I = 0, J = 0;
+                tile_ij(NT, t, I, J);
+                acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[I], op[J], acc[u], 0, 0, 0);
+            }
+        }
+    }
+}
+
+template <int NP, int MODE, bool VEC>
+__device__ __forceinline__ void
+pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__restrict__ Rt,
+               const double *__restrict__ dinv, double *__restrict__ part_out,
+               const Ctl *__restrict__ ctl, int pass, int final_gram, int64_t p0, int64_t p1)
+{
+    constexpr int WAVES = 4;
+    constexpr int PR = 64;
+    constexpr int NT = NP / 16;
+    constexpr int T = NT * (NT + 1) / 2;
+    constexpr int TPW = (T + WAVES - 1) / WAVES;
+    constexpr int NOFF = NT * (NT - 1) / 2;
+    constexpr int S = NP + 2;
+    constexpr int PP = PR * NP / 2 / (WAVES * 64);  // double pairs per thread per panel
+    __shared__ __attribute__((aligned(16))) double P[PR * S];
+    __shared__ double bl[NOFF * 4 * 64];
+
+    if (!gate(ctl, pass)) return;
+    const bool want_gram = MODE == 1 && gram_needed(ctl, pass, final_gram);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, lk = lane >> 4;
+    const int n = p.n;
+
+    for (int idx = threadIdx.x; idx < NOFF * 4 * 64; idx += WAVES * 64) {
+        const int l = idx & 63, s4 = (idx >> 6) & 3, pi = idx >> 8;
+        int J = 1, K = pi;
+        while (K >= J) {
+            K -= J;
+            ++J;
+        }
+        bl[idx] = -as_cview(Rt)[(16 * K + 4 * s4 + (l >> 4)) * NP + 16 * J + (l & 15)];
+    }
+
+    d4 acc[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) acc[u] = (d4){0.0, 0.0, 0.0, 0.0};
+
+    double2 pre[PP];
+    auto load_panel = [&](int64_t pnl) {
+        const int64_t rb = pnl * PR;
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int e2 = threadIdx.x + WAVES * 64 * i;
+            const int r = e2 / (NP / 2), c = 2 * (e2 % (NP / 2));
+            const int64_t row = rb + r;
+            if (VEC) {
+                const bool ok = row < p.m && c < n;
+                const int64_t rr = row < p.m ? row : p.m - 1;
+                const int cc = c < n ? c : 0;
+                const d2 v = *reinterpret_cast<gview<const d2>>(as_global(p.X) + rr * p.ldx + cc);
+                pre[i] = ok ? make_double2(v.x, v.y) : make_double2(0.0, 0.0);
+            } else {
+                double a = 0.0, b = 0.0;
+                if (row < p.m) {
+                    const gview<const double> src = as_global(p.X) + row * p.ldx + c;
+                    if (c < n) a = src[0];
+                    if (c + 1 < n) b = src[1];
+                }
+                pre[i] = make_double2(a, b);
+            }
+        }
+    };
+    if (p0 < p1) load_panel(p0);
+    for (int64_t pn = p0; pn < p1; ++pn) {
+        const int64_t r0 = pn * PR;
+        __syncthreads();  // the previous panel is no longer read
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int e2 = threadIdx.x + WAVES * 64 * i;
+            const int r = e2 / (NP / 2), c = 2 * (e2 % (NP / 2));
+            *reinterpret_cast<double2 *>(P + r * S + c) = pre[i];
+        }
+        __syncthreads();
+        if (pn + 1 < p1) load_panel(pn + 1);
+
+        // ---- substitution of rows 16 wv .. 16 wv + 15
+        const int R0 = 16 * wv;
+        const int64_t off = pn & (int64_t)p.zero;
+        int pi0 = 0;
+#pragma unroll
+        for (int J = 0; J < NT; ++J) {
+            if (J > 0) {
+                double *blk = P + (R0 + lk) * S + 16 * J + li;
+                d4 d;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) d[r] = blk[4 * r * S];
+                const double *arow = P + (R0 + li) * S + lk;
+                int pi = pi0;
+#pragma unroll
+                for (int K = 0; K < J; ++K, ++pi)
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4)
+                        d = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * K + 4 * s4], bl[(pi * 4 + s4) * 64 + lane], d,
+                                                                 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) blk[4 * r * S] = d[r];
+                pi0 += J;
+                wave_sync();
+            }
+            if (lane < 16) {
+                double *mr = P + (R0 + lane) * S + 16 * J;
+                double t[16];
+#pragma unroll
+                for (int c = 0; c < 16; c += 2) {
+                    const double2 v = *reinterpret_cast<const double2 *>(mr + c);
+                    t[c] = v.x;
+                    t[c + 1] = v.y;
+                }
+                int64_t offk = off;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    if ((k & 1) == 0) asm volatile("" : "+s"(offk));
+                    const cview<double> Rd = as_cview(Rt) + offk + (16 * J) * NP + 16 * J;
+                    const double qk = t[k] * as_cview(dinv)[offk + 16 * J + k];
+                    t[k] = qk;
+#pragma unroll
+                    for (int j = k + 1; j < 16; ++j) t[j] = __builtin_fma(-qk, Rd[k * NP + j], t[j]);
+                }
+#pragma unroll
+                for (int c = 0; c < 16; c += 2) *reinterpret_cast<double2 *>(mr + c) = make_double2(t[c], t[c + 1]);
+            }
+            wave_sync();
+        }
+        __syncthreads();
+
+        // ---- Q panel -> HBM
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int e2 = threadIdx.x + WAVES * 64 * i;
+            const int r = e2 / (NP / 2), c = 2 * (e2 % (NP / 2));
+            const int64_t row = r0 + r;
+            if (row < p.m && c < n) {
+                const double2 v = *reinterpret_cast<const double2 *>(P + r * S + c);
+                const gview<double> dst = as_global(Qout) + row * p.ldq + c;
+                if (VEC) {
+                    *reinterpret_cast<gview<d2>>(dst) = (d2){v.x, v.y};
+                } else {
+                    dst[0] = v.x;
+                    if (c + 1 < n) dst[1] = v.y;
+                }
+            }
+        }
+
+        // ---- Gram tiles of this wave over the 64 rows
+        if (want_gram) {
+            const double *src = P + lk * S + li;
+            switch (wv) {
+            case 0: wide_gram<NP, 0, WAVES, TPW, PR, S>(acc, src); break;
+            case 1: wide_gram<NP, 1, WAVES, TPW, PR, S>(acc, src); break;
+            case 2: wide_gram<NP, 2, WAVES, TPW, PR, S>(acc, src); break;
+            default: wide_gram<NP, 3, WAVES, TPW, PR, S>(acc, src); break;
+            }
+        }
+    }
+    if (!want_gram) return;
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int t = wv + u * WAVES;
+        if (t < T) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part_out[t * 256 + r * 64 + lane] = acc[u][r];
+        }
+    }
+}
+
+template <int NP, int MODE, bool VEC>
+__global__ void __launch_bounds__(256)
+k_pass_wide(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
             const double *__restrict__ dinv, double *__restrict__ partials,
             const Ctl *__restrict__ ctl, int pass, int final_gram)
 {
-    // Qout == p.Q; passing it as a restrict parameter lets the factor loads stay scalar.
-    constexpr int WAVES = PR == 64 ? 4 : 8;
     constexpr int NT = NP / 16;
-    constexpr int T = NT * (NT + 1) / 2;
-    pass_tile_body<NP, MODE, F32, VEC, PR>(p, Qout, Rt, dinv, partials + (int64_t)blockIdx.x * (T * 256), ctl,
-                                           pass, final_gram, (int64_t)blockIdx.x * WAVES,
-                                           (int64_t)gridDim.x * WAVES, (p.m + PR - 1) / PR);
+    constexpr int64_t E = (int64_t)NT * (NT + 1) / 2 * 256;
+    const int64_t npanels = (p.m + 63) / 64;
+    const int64_t per = (npanels + gridDim.x - 1) / gridDim.x;
+    const int64_t p0 = (int64_t)blockIdx.x * per;
+    const int64_t p1 = (p0 + per < npanels) ? p0 + per : npanels;
+    pass_wide_body<NP, MODE, VEC>(p, Qout, Rt, dinv, partials + (int64_t)blockIdx.x * E, ctl, pass, final_gram,
+                                  p0 < p1 ? p0 : p1, p1);
 }
 
-// Batched form: workgroup b processes task b (rows [r0, r1) of one instance); pass > 1 reads
-// the instance's Q.
-template <int NP, int MODE, bool F32, bool VEC, int PR>
-__global__ void __launch_bounds__(PR == 64 ? 256 : 512)
-k_pass_tile_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__ tasks,
+template <int NP, int MODE, bool VEC>
+__global__ void __launch_bounds__(256)
+k_pass_wide_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__ tasks,
               double *__restrict__ partials, int pass, int final_gram)
 {
-    constexpr int WAVES = PR == 64 ? 4 : 8;
     constexpr int NT = NP / 16;
-    constexpr int T = NT * (NT + 1) / 2;
+    constexpr int64_t E = (int64_t)NT * (NT + 1) / 2 * 256;
     const BatchTask t = load_cview(tasks + blockIdx.x);
     const BatchInst I = load_cview(insts + t.inst);
     Problem p = I.p;
@@ -310,9 +547,9 @@ k_pass_tile_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__
         p.X = p.Q;
         p.ldx = p.ldq;
     }
-    pass_tile_body<NP, MODE, F32, VEC, PR>(p, p.Q, factor_of(I.w, NP, pass), dinv_of(I.w, NP, pass),
-                                           partials + (int64_t)blockIdx.x * (T * 256), I.w.ctl, pass,
-                                           final_gram, t.r0 / PR, WAVES, (t.r1 + PR - 1) / PR);
+    pass_wide_body<NP, MODE, VEC>(p, p.Q, factor_of(I.w, NP, pass), dinv_of(I.w, NP, pass),
+                                  partials + (int64_t)blockIdx.x * E, I.w.ctl, pass, final_gram, t.r0 / 64,
+                                  (t.r1 + 63) / 64);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -692,17 +929,17 @@ static void launch_small_v(hipStream_t s, const Problem &p, const Work &w, int m
     dim3 grid(w.nwg), block(PR == 64 ? 256 : 512);
     if (mode == 0) {
         if (f32)
-            hipLaunchKernelGGL((k_pass_tile<NP, 0, true, VEC, PR>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
-                               w.partials, w.ctl, pass, final_gram);
+            hipLaunchKernelGGL((k_pass_tile<NP, 0, true, VEC, PR, false>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
+                               w.partials, w.ctl, pass, final_gram, nullptr, nullptr);
         else
-            hipLaunchKernelGGL((k_pass_tile<NP, 0, false, VEC, PR>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
-                               w.partials, w.ctl, pass, final_gram);
+            hipLaunchKernelGGL((k_pass_tile<NP, 0, false, VEC, PR, false>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
+                               w.partials, w.ctl, pass, final_gram, nullptr, nullptr);
     } else if (mode == 1) {
-        hipLaunchKernelGGL((k_pass_tile<NP, 1, false, VEC, PR>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
-                           w.partials, w.ctl, pass, final_gram);
+        hipLaunchKernelGGL((k_pass_tile<NP, 1, false, VEC, PR, false>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
+                           w.partials, w.ctl, pass, final_gram, nullptr, nullptr);
     } else {
-        hipLaunchKernelGGL((k_pass_tile<NP, 2, false, VEC, PR>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
-                           w.partials, w.ctl, pass, final_gram);
+        hipLaunchKernelGGL((k_pass_tile<NP, 2, false, VEC, PR, false>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
+                           w.partials, w.ctl, pass, final_gram, nullptr, nullptr);
     }
 }
 
@@ -752,6 +989,24 @@ static hipError_t launch_trsm_big(hipStream_t s, const Problem &p, const Work &w
     return hipGetLastError();
 }
 
+template <int NP>
+static hipError_t launch_wide(hipStream_t s, const Problem &p, const Work &w, int mode, int pass, int final_gram)
+{
+    const bool vec = (reinterpret_cast<uintptr_t>(p.X) & 15) == 0 && (p.ldx & 1) == 0 &&
+                     (reinterpret_cast<uintptr_t>(p.Q) & 15) == 0 && (p.ldq & 1) == 0 && (p.n & 1) == 0;
+    dim3 grid(w.nwg), block(256);
+    const double *Rt = factor_of(w, NP, pass), *dv = dinv_of(w, NP, pass);
+    if (mode == 1 && vec)
+        hipLaunchKernelGGL((k_pass_wide<NP, 1, true>), grid, block, 0, s, p, p.Q, Rt, dv, w.partials, w.ctl, pass, final_gram);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_pass_wide<NP, 1, false>), grid, block, 0, s, p, p.Q, Rt, dv, w.partials, w.ctl, pass, final_gram);
+    else if (vec)
+        hipLaunchKernelGGL((k_pass_wide<NP, 2, true>), grid, block, 0, s, p, p.Q, Rt, dv, w.partials, w.ctl, pass, final_gram);
+    else
+        hipLaunchKernelGGL((k_pass_wide<NP, 2, false>), grid, block, 0, s, p, p.Q, Rt, dv, w.partials, w.ctl, pass, final_gram);
+    return hipGetLastError();
+}
+
 static hipError_t gram_generic(hipStream_t s, const Problem &p, const Work &w, int pass, bool f32,
                                bool obl, bool euc, int final_gram)
 {
@@ -782,6 +1037,12 @@ hipError_t launch_pass(hipStream_t s, const Problem &p, const Work &w, int mode,
         prof_after(s);
         return e;
     }
+    if (p.np == 128 && mode == 1 && !oblique_gram) {
+        prof_before(s, "trsm_gram");
+        e = launch_wide<128>(s, p, w, 1, pass, final_gram);
+        prof_after(s);
+        return e;
+    }
     // Generic path: separate substitution and Gram kernels.
     if (mode >= 1) {
         prof_before(s, "trsm");
@@ -789,7 +1050,7 @@ hipError_t launch_pass(hipStream_t s, const Problem &p, const Work &w, int mode,
         case 16: e = launch_small<16>(s, p, w, 2, pass, false, 0); break;
         case 32: e = launch_small<32>(s, p, w, 2, pass, false, 0); break;
         case 64: e = launch_small<64>(s, p, w, 2, pass, false, 0); break;
-        case 128: e = launch_trsm_big<128>(s, p, w, pass); break;
+        case 128: e = launch_wide<128>(s, p, w, 2, pass, 0); break;
         case 256: e = launch_trsm_big<256>(s, p, w, pass); break;
         default: e = hipErrorInvalidValue;
         }
@@ -826,14 +1087,14 @@ static void launch_small_b(hipStream_t s, const BatchClass &c, int mode, int pas
     constexpr int PR = kPanelRows;
     dim3 grid((unsigned)c.ntasks), block(PR == 64 ? 256 : 512);
     if (mode == 0 && f32)
-        hipLaunchKernelGGL((k_pass_tile_b<NP, 0, true, VEC, PR>), grid, block, 0, s, c.insts, c.tasks, c.partials,
-                           pass, final_gram);
+        hipLaunchKernelGGL((k_pass_tile<NP, 0, true, VEC, PR, true>), grid, block, 0, s, Problem{}, nullptr, nullptr, nullptr,
+                           c.partials, nullptr, pass, final_gram, c.insts, c.tasks);
     else if (mode == 0)
-        hipLaunchKernelGGL((k_pass_tile_b<NP, 0, false, VEC, PR>), grid, block, 0, s, c.insts, c.tasks, c.partials,
-                           pass, final_gram);
+        hipLaunchKernelGGL((k_pass_tile<NP, 0, false, VEC, PR, true>), grid, block, 0, s, Problem{}, nullptr, nullptr, nullptr,
+                           c.partials, nullptr, pass, final_gram, c.insts, c.tasks);
     else
-        hipLaunchKernelGGL((k_pass_tile_b<NP, 1, false, VEC, PR>), grid, block, 0, s, c.insts, c.tasks, c.partials,
-                           pass, final_gram);
+        hipLaunchKernelGGL((k_pass_tile<NP, 1, false, VEC, PR, true>), grid, block, 0, s, Problem{}, nullptr, nullptr, nullptr,
+                           c.partials, nullptr, pass, final_gram, c.insts, c.tasks);
 }
 
 template <int NP>
@@ -849,6 +1110,17 @@ template <int NP, int WAVES>
 static void launch_big_b(hipStream_t s, const BatchClass &c, int mode, int pass, bool f32, int final_gram)
 {
     dim3 grid((unsigned)c.ntasks);
+    if (NP == 128 && mode == 1) {
+        prof_before(s, "b_trsm_gram");
+        if (c.vec)
+            hipLaunchKernelGGL((k_pass_wide_b<128, 1, true>), grid, dim3(256), 0, s, c.insts, c.tasks, c.partials,
+                               pass, final_gram);
+        else
+            hipLaunchKernelGGL((k_pass_wide_b<128, 1, false>), grid, dim3(256), 0, s, c.insts, c.tasks, c.partials,
+                               pass, final_gram);
+        prof_after(s);
+        return;
+    }
     if (mode >= 1) {
         prof_before(s, "b_trsm");
         hipLaunchKernelGGL((k_trsm_big_b<NP>), grid, dim3(256), 0, s, c.insts, c.tasks, pass);

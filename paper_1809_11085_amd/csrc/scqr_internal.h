@@ -173,7 +173,7 @@ struct BatchTask {
     int32_t pad;
     int64_t r0, r1;
 };
-constexpr int kBatchRowAlign = 32;
+constexpr int kBatchRowAlign = 64;
 struct BatchClass {
     int np;
     int ninst, ntasks;
