@@ -235,6 +235,111 @@ def extra_c5(scqr, synth):
     return res
 
 
+# short names of the single-problem kernels as the library's profiling records them
+KERNEL_PATTERNS = [
+    ("trsm_gram", r"k_pass_tile<\d+, 1, false, (true|false), 32(, false)?>"),
+    ("gram", r"k_pass_tile<\d+, 0, false, (true|false), 32(, false)?>"),
+    ("trsm_gram", r"k_pass_wide<\d+, 1, (true|false)>"),
+    ("trsm", r"k_pass_wide<\d+, 2, (true|false)>"),
+    ("chol", r"k_chol<\d+>"),
+    ("reduce", r"k_reduce\("),
+    ("finalize_r", r"k_finalize_r<\d+>"),
+]
+
+
+def short_name(kname):
+    import re
+
+    for short, pat in KERNEL_PATTERNS:
+        if re.search(pat, kname):
+            return short
+    return None
+
+
+def summarize_profile(d, workload):
+    """Summaries of a rocprofv3 kernel trace and of FETCH_SIZE / WRITE_SIZE counter runs of the
+    same bench command, with the counters scaled by what they read for a device copy of known
+    size.  Writes profiles/<kernel>_<workload>.md (text) and _counters.json (read by the
+    roofline object of later runs while the kernel sources are unchanged)."""
+    import csv
+
+    import numpy as np
+
+    def rows(sub, name):
+        with open(os.path.join(d, sub, name)) as fh:
+            return list(csv.DictReader(fh))
+
+    m, n = WORKLOADS[workload][:2]
+    trace = rows("trace", "run_kernel_trace.csv")
+    stats = rows("trace", "run_kernel_stats.csv")
+    per = {}
+    for r in trace:
+        sn = short_name(r["Kernel_Name"])
+        if sn:
+            per.setdefault(sn, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6)
+    dom = max(per, key=lambda k: sum(per[k]))
+    durs = np.array(per[dom])
+    act = durs[durs >= 0.25 * durs.max()]
+
+    def counter(sub):
+        vals = [float(r["Counter_Value"]) for r in rows(sub, "run_counter_collection.csv")
+                if short_name(r["Kernel_Name"]) == dom]
+        v = np.array(vals)
+        return float(np.mean(v[v >= 0.25 * v.max()]))
+
+    def calib(sub):
+        v = [float(r["Counter_Value"]) for r in rows(sub, "run_counter_collection.csv")
+             if "copyBuffer" in r["Kernel_Name"]]
+        return (1 << 30) / 1024.0 / float(np.median(v))
+
+    fetch, write = counter("fetch"), counter("write")
+    fs, ws = calib("cfetch"), calib("cwrite")
+    traffic = fetch * 1024 * fs + write * 1024 * ws
+    alg = {"trsm_gram": 16 * m * n, "trsm": 16 * m * n, "gram": 8 * m * n}.get(dom, 16 * m * n)
+    base = "python3 -u bench.py --workload %s --steps 5 --warmup 2 --no-cpu-baseline --no-accuracy --no-extras" % workload
+    cmds = {
+        "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/trace -o run -- " + base,
+        "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/fetch -o run -- " + base.replace("--steps 5 --warmup 2", "--steps 2 --warmup 1"),
+        "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/write -o run -- " + base.replace("--steps 5 --warmup 2", "--steps 2 --warmup 1"),
+        "copy_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/cfetch -o run -- python3 -u bench.py --copy-calibration",
+        "copy_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/cwrite -o run -- python3 -u bench.py --copy-calibration",
+        "summary": "python3 bench.py --workload %s --summarize-profile gpurun_out/prof" % workload,
+    }
+    out = {"kernel": dom, "workload": workload, "source_hash": source_hash(),
+           "avg_active_ms_rocprof": float(np.mean(act)), "active_launches": int(act.size),
+           "fetch_kib_per_launch": fetch, "write_kib_per_launch": write,
+           "fetch_scale": fs, "write_scale": ws, "hbm_bytes_per_launch": traffic,
+           "algorithmic_bytes_per_launch": alg, "traffic_over_algorithmic": traffic / alg,
+           "commands": cmds}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"{dom}_{workload}_counters.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    lines = [f"# rocprofv3 summary: `{dom}` kernel, workload {workload} ({WORKLOADS[workload][4]})", "",
+             "Commands (run from the repository root on one MI355X):", ""]
+    lines += [f"* {k}: `{v}`" for k, v in cmds.items()]
+    lines += ["", "## Kernel statistics (`--kernel-trace --stats`, run_kernel_stats.csv)", "",
+              "| kernel | calls | total ms | avg us | min us | max us |", "|---|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]:
+        nm = r["Name"].split("(")[0].replace("|", "/")
+        lines.append(f"| `{nm[:70]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} |")
+    lines += ["", f"## `{dom}`", "",
+              f"* launches that ran (duration >= 25% of the longest; the others were skipped by the device "
+              f"schedule): {act.size}, average {np.mean(act) * 1e3:.1f} us, min {act.min() * 1e3:.1f} us, "
+              f"max {act.max() * 1e3:.1f} us",
+              f"* algorithmic bytes per launch: {alg} (16 m n: read X or Q once, write Q once)",
+              f"* FETCH_SIZE {fetch:.1f} KiB and WRITE_SIZE {write:.1f} KiB per launch; a device copy of 1 GiB "
+              f"reads {1048576 / fs:.1f} KiB FETCH_SIZE and {1048576 / ws:.1f} KiB WRITE_SIZE, so the scale "
+              f"factors are {fs:.4f} and {ws:.4f}",
+              f"* HBM traffic per launch: {traffic:.4e} B = {traffic / alg:.4f} x algorithmic",
+              f"* achieved (algorithmic bytes / rocprofv3 average duration): "
+              f"{alg / np.mean(act) / 1e6:.1f} GB/s of 8000 GB/s",
+              f"* source hash of the kernels profiled: {out['source_hash']}", ""]
+    with open(os.path.join(ROOT, "profiles", f"{dom}_{workload}.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +350,9 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="write profiles/<kernel>_<workload>.md and _counters.json from the rocprofv3 "
+                         "outputs under DIR (trace/, fetch/, write/, cfetch/, cwrite/)")
     ap.add_argument("--extras", default="c2b,c3,c4,c5")
     args = ap.parse_args()
 
@@ -262,6 +370,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile, args.workload)
         return
     if not os.path.exists(scqr.LIB_PATH):
         from paper_1809_11085_amd import build as hipbuild
