@@ -724,7 +724,76 @@ __device__ void finalize_small(const Problem &p, const Work &w, int passes)
     }
 }
 
-// NP >= 128: the running product in LDS (NP = 128) or in the global ping-pong buffers.
+// NP = 128: the running product in LDS; each factor is staged 16 columns at a time, transposed,
+// and thread t accumulates rows 64 (t / 128) .. + 63 of column t % 128 over k in increasing
+// order (the terms outside i <= k <= j are exact zeros, as in finalize_small).
+template <int NP>
+__device__ void finalize_mid(const Problem &p, const Work &w, int passes)
+{
+    constexpr int S = NP + 1;
+    constexpr int KC = 16;
+    constexpr int ST = NP + 2;
+    constexpr int GR = 256 / NP;
+    constexpr int ROWS = NP / GR;
+    constexpr int PER = NP * NP / 256;
+    constexpr int CH = KC * NP / 256;  // staged values per thread per chunk
+    __shared__ double A[NP * S];
+    __shared__ __attribute__((aligned(16))) double ft[KC * ST];
+    const int t = threadIdx.x, j = t % NP, g = t / NP;
+    const int n = p.n;
+    for (int u0 = 0; u0 < PER; u0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = (u0 + u) * 256 + t;
+            v[u] = passes >= 1 ? w.Rhist[idx] : ((idx / NP == idx % NP) ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = (u0 + u) * 256 + t;
+            A[(idx / NP) * S + idx % NP] = v[u];
+        }
+    }
+    for (int q = 2; q <= passes; ++q) {
+        const double *F = w.Rhist + (int64_t)(q - 1) * NP * NP;
+        double acc[ROWS];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) acc[r] = 0.0;
+        for (int k0 = 0; k0 < NP; k0 += KC) {
+            double v[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int e = c * 256 + t;
+                v[c] = F[(e / KC) * NP + k0 + e % KC];
+            }
+            __syncthreads();  // the previous chunk (and the previous product) is consumed
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int e = c * 256 + t;
+                ft[(e % KC) * ST + e / KC] = v[c];
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int kk = 0; kk < KC; ++kk) {
+                const double a = A[(k0 + kk) * S + j];
+                const double *fk = ft + kk * ST + g * ROWS;
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) acc[r] = __builtin_fma(fk[r], a, acc[r]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) A[(g * ROWS + r) * S + j] = acc[r];
+    }
+    __syncthreads();
+    for (int u = 0; u < PER; ++u) {
+        const int idx = u * 256 + t;
+        const int i = idx / NP, jj = idx % NP;
+        if (i < n && jj < n) p.R[(int64_t)i * p.ldr + jj] = (jj >= i) ? A[i * S + jj] : 0.0;
+    }
+}
+
+// NP = 256: the running product in the global ping-pong buffers.
 template <int NP>
 __device__ void finalize_big(const Problem &p, const Work &w)
 {
@@ -813,6 +882,8 @@ __global__ void __launch_bounds__(256) k_finalize_r(Problem p, Work w)
 {
     if constexpr (NP <= 64)
         finalize_small<NP>(p, w, w.ctl->pass);
+    else if constexpr (NP == 128)
+        finalize_mid<NP>(p, w, w.ctl->pass);
     else
         finalize_big<NP>(p, w);
 }
@@ -823,6 +894,8 @@ __global__ void __launch_bounds__(256) k_finalize_b(const BatchInst *__restrict_
     const BatchInst I = load_cview(insts + blockIdx.x);
     if constexpr (NP <= 64)
         finalize_small<NP>(I.p, I.w, I.w.ctl->pass);
+    else if constexpr (NP == 128)
+        finalize_mid<NP>(I.p, I.w, I.w.ctl->pass);
     else
         finalize_big<NP>(I.p, I.w);
 }

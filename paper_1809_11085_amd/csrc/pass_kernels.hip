@@ -553,6 +553,207 @@ k_pass_wide_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__
 }
 
 // ------------------------------------------------------------------------------------------
+// Gram for n <= 128 with 64-row panels shared by 4 waves (wave w owns the upper tiles
+// t = w, w+4, ...; its operands are read from LDS at wave-uniform tile offsets).  The next
+// panel's loads are issued before the current panel's MFMAs.
+//   OBL: B-Gram X^T (B X), B tridiagonal: the panel carries one halo row above and below and
+//        Y = B X is formed once per panel in LDS, (B x)_k = off_{k-1} x_{k-1} + diag_k x_k +
+//        off_k x_{k+1}.
+//   EUC: with OBL, also X^T X (second half of the partial) and the workgroup's Gershgorin
+//        maximum of B (for the first-pass shift of equation (eq:finds2B)).
+//   F32: binary32 MFMA over each 64-row panel, added to the binary64 tiles after the panel.
+//   BATCH: workgroup b takes task b of the device task table; otherwise workgroup b takes a
+//        contiguous share of the problem's panels.
+template <int NP, bool OBL, bool EUC, bool F32, bool BATCH>
+__global__ void __launch_bounds__(256)
+k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
+            const Ctl *__restrict__ ctl, int pass, int final_gram,
+            const BatchInst *__restrict__ insts, const BatchTask *__restrict__ tasks)
+{
+    constexpr int PR = 64;
+    constexpr int H = OBL ? 1 : 0;
+    constexpr int NT = NP / 16;
+    constexpr int T = NT * (NT + 1) / 2;
+    constexpr int TPW = (T + 3) / 4;
+    constexpr int S = NP + 2;
+    constexpr int PP = PR * NP / 2 / 256;  // double pairs per thread per panel
+    constexpr int64_t E = (int64_t)T * 256;
+    __shared__ __attribute__((aligned(16))) double xs[(PR + 2 * H) * S];
+    __shared__ __attribute__((aligned(16))) double ys[OBL ? PR * S : 1];
+    __shared__ double cs[OBL ? 3 * PR : 1];
+    __shared__ double gm[EUC ? 256 : 1];
+
+    int64_t p0, p1;
+    if constexpr (BATCH) {
+        const BatchTask tk = load_cview(tasks + blockIdx.x);
+        const BatchInst I = load_cview(insts + tk.inst);
+        p = I.p;
+        if (pass >= 1) {  // the Gram of pass >= 1 reads the Q its substitution just wrote
+            p.X = p.Q;
+            p.ldx = p.ldq;
+        }
+        ctl = I.w.ctl;
+        p0 = tk.r0 / PR;
+        p1 = (tk.r1 + PR - 1) / PR;
+    } else {
+        const int64_t npanels = (p.m + PR - 1) / PR;
+        const int64_t per = (npanels + gridDim.x - 1) / gridDim.x;
+        p0 = (int64_t)blockIdx.x * per;
+        p1 = (p0 + per < npanels) ? p0 + per : npanels;
+        if (p0 > p1) p0 = p1;
+    }
+    if (!gate(ctl, pass)) return;
+    if (!gram_needed(ctl, pass, final_gram)) return;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int n = p.n;
+
+    d4 acc[TPW], acce[EUC ? TPW : 1];
+    f4 a32[F32 ? TPW : 1];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) acc[u] = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < (EUC ? TPW : 1); ++u) acce[u] = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < (F32 ? TPW : 1); ++u) a32[u] = (f4){0.f, 0.f, 0.f, 0.f};
+    double bm = 0.0;
+    // column offsets (16 I, 16 J) of this wave's tiles t = wv + 4u
+    int ti[TPW], tj[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        int I = 0, J = 0;
+        tile_ij(NT, wv + 4 * u < T ? wv + 4 * u : 0, I, J);
+        ti[u] = 16 * I;
+        tj[u] = 16 * J;
+    }
+
+    double2 pre[PP], hal = make_double2(0.0, 0.0);
+    double clo = 0.0, cd = 0.0, cup = 0.0;
+    auto pair_at = [&](int64_t row, int c) -> double2 {
+        double a = 0.0, b = 0.0;
+        if (row >= 0 && row < p.m) {
+            const gview<const double> src = as_global(p.X) + row * p.ldx + c;
+            if (c < n) a = src[0];
+            if (c + 1 < n) b = src[1];
+        }
+        return make_double2(a, b);
+    };
+    auto load_panel = [&](int64_t pnl) {
+        const int64_t rb = pnl * PR;
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int e2 = t + 256 * i;
+            pre[i] = pair_at(rb + e2 / (NP / 2), 2 * (e2 % (NP / 2)));
+        }
+        if (OBL) {
+            if (t < NP) {  // halo rows rb - 1 (t < NP/2) and rb + PR
+                const int hr = t / (NP / 2), c = 2 * (t % (NP / 2));
+                hal = pair_at(hr == 0 ? rb - 1 : rb + PR, c);
+            }
+            if (t < PR) {
+                const int64_t row = rb + t;
+                clo = cd = cup = 0.0;
+                if (row < p.m) {
+                    cd = as_global(p.bdiag)[row];
+                    if (row > 0) clo = as_global(p.boff)[row - 1];
+                    if (row + 1 < p.m) cup = as_global(p.boff)[row];
+                }
+            }
+        }
+    };
+    if (p0 < p1) load_panel(p0);
+    for (int64_t pn = p0; pn < p1; ++pn) {
+        __syncthreads();  // the previous panel is no longer read
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int e2 = t + 256 * i;
+            *reinterpret_cast<double2 *>(xs + (H + e2 / (NP / 2)) * S + 2 * (e2 % (NP / 2))) = pre[i];
+        }
+        if (OBL) {
+            if (t < NP) {
+                const int hr = t / (NP / 2), c = 2 * (t % (NP / 2));
+                *reinterpret_cast<double2 *>(xs + (hr == 0 ? 0 : PR + 1) * S + c) = hal;
+            }
+            if (t < PR) {
+                cs[3 * t] = clo;
+                cs[3 * t + 1] = cd;
+                cs[3 * t + 2] = cup;
+                if (EUC && pn * PR + t < p.m) {
+                    double g = fabs(clo) + fabs(cd);
+                    g = g + fabs(cup);
+                    bm = g > bm ? g : bm;
+                }
+            }
+        }
+        __syncthreads();
+        if (pn + 1 < p1) load_panel(pn + 1);
+        if (OBL) {
+            // Y = B X for the 64 panel rows
+#pragma unroll
+            for (int i = 0; i < PR * NP / 256; ++i) {
+                const int e = t + 256 * i;
+                const int r = e / NP, c = e % NP;
+                const double *xc = xs + (r + 1) * S + c;
+                const double bx = cs[3 * r] * xc[-S] + cs[3 * r + 1] * xc[0];
+                ys[r * S + c] = bx + cs[3 * r + 2] * xc[S];
+            }
+            __syncthreads();
+        }
+        const double *xsrc = xs + (H + (lane >> 4)) * S + (lane & 15);
+        const double *ysrc = OBL ? ys + (lane >> 4) * S + (lane & 15) : xsrc;
+#pragma unroll 2
+        for (int s4 = 0; s4 < PR / 4; ++s4) {
+            const double *xr = xsrc + 4 * s4 * S;
+            const double *yr = ysrc + 4 * s4 * S;
+#pragma unroll
+            for (int u = 0; u < TPW; ++u) {
+                if (wv + 4 * u < T) {
+                    const double a = xr[ti[u]];
+                    const double b = yr[tj[u]];
+                    if (F32)
+                        a32[F32 ? u : 0] =
+                            __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, a32[F32 ? u : 0], 0, 0, 0);
+                    else
+                        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
+                    if (EUC)
+                        acce[EUC ? u : 0] =
+                            __builtin_amdgcn_mfma_f64_16x16x4f64(a, xr[tj[u]], acce[EUC ? u : 0], 0, 0, 0);
+                }
+            }
+        }
+        if (F32) {
+#pragma unroll
+            for (int u = 0; u < TPW; ++u) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[u][r] += (double)a32[F32 ? u : 0][r];
+                a32[F32 ? u : 0] = (f4){0.f, 0.f, 0.f, 0.f};
+            }
+        }
+    }
+    double *out = partials + (int64_t)blockIdx.x * (EUC ? 2 * E : E);
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int tt = wv + u * 4;
+        if (tt < T) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                out[tt * 256 + r * 64 + lane] = acc[u][r];
+                if (EUC) out[E + tt * 256 + r * 64 + lane] = acce[EUC ? u : 0][r];
+            }
+        }
+    }
+    if (EUC) {
+        gm[t] = bm;
+        __syncthreads();
+        if (t == 0) {
+            double g = 0.0;
+            for (int i = 0; i < 256; ++i) g = gm[i] > g ? gm[i] : g;
+            bmax[blockIdx.x] = g;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // Row-wise substitution for n > 64, one row per thread, 64-column blocks: block J starts from
 // x_J, receives -q_k r_kj for every earlier k in increasing order (solved values are re-read
 // from the thread's own output row), then is solved against the diagonal block.
@@ -1007,14 +1208,36 @@ static hipError_t launch_wide(hipStream_t s, const Problem &p, const Work &w, in
     return hipGetLastError();
 }
 
+template <int NP>
+static hipError_t launch_gram_wide(hipStream_t s, const Problem &p, const Work &w, int pass, bool f32,
+                                   bool obl, bool euc, int final_gram)
+{
+    dim3 grid(w.nwg), block(256);
+    const BatchInst *ni = nullptr;
+    const BatchTask *nt = nullptr;
+    if (obl && euc)
+        hipLaunchKernelGGL((k_gram_wide<NP, true, true, false, false>), grid, block, 0, s, p, w.partials, w.bmax,
+                           w.ctl, pass, final_gram, ni, nt);
+    else if (obl)
+        hipLaunchKernelGGL((k_gram_wide<NP, true, false, false, false>), grid, block, 0, s, p, w.partials, w.bmax,
+                           w.ctl, pass, final_gram, ni, nt);
+    else if (f32)
+        hipLaunchKernelGGL((k_gram_wide<NP, false, false, true, false>), grid, block, 0, s, p, w.partials, w.bmax,
+                           w.ctl, pass, final_gram, ni, nt);
+    else
+        hipLaunchKernelGGL((k_gram_wide<NP, false, false, false, false>), grid, block, 0, s, p, w.partials, w.bmax,
+                           w.ctl, pass, final_gram, ni, nt);
+    return hipGetLastError();
+}
+
 static hipError_t gram_generic(hipStream_t s, const Problem &p, const Work &w, int pass, bool f32,
                                bool obl, bool euc, int final_gram)
 {
     switch (p.np) {
-    case 16: return launch_gram_lds<16, 1>(s, p, w, pass, f32, obl, euc, final_gram);
-    case 32: return launch_gram_lds<32, 4>(s, p, w, pass, f32, obl, euc, final_gram);
-    case 64: return launch_gram_lds<64, 4>(s, p, w, pass, f32, obl, euc, final_gram);
-    case 128: return launch_gram_lds<128, 4>(s, p, w, pass, f32, obl, euc, final_gram);
+    case 16: return launch_gram_wide<16>(s, p, w, pass, f32, obl, euc, final_gram);
+    case 32: return launch_gram_wide<32>(s, p, w, pass, f32, obl, euc, final_gram);
+    case 64: return launch_gram_wide<64>(s, p, w, pass, f32, obl, euc, final_gram);
+    case 128: return launch_gram_wide<128>(s, p, w, pass, f32, obl, euc, final_gram);
     case 256: return launch_gram_lds<256, 8>(s, p, w, pass, f32, obl, euc, final_gram);
     }
     return hipErrorInvalidValue;
@@ -1127,12 +1350,20 @@ static void launch_big_b(hipStream_t s, const BatchClass &c, int mode, int pass,
         prof_after(s);
     }
     prof_before(s, f32 ? "b_gram_f32" : "b_gram");
-    if (f32)
+    if constexpr (NP == 128) {
+        if (f32)
+            hipLaunchKernelGGL((k_gram_wide<NP, false, false, true, true>), grid, dim3(256), 0, s, Problem{},
+                               c.partials, nullptr, nullptr, pass, final_gram, c.insts, c.tasks);
+        else
+            hipLaunchKernelGGL((k_gram_wide<NP, false, false, false, true>), grid, dim3(256), 0, s, Problem{},
+                               c.partials, nullptr, nullptr, pass, final_gram, c.insts, c.tasks);
+    } else if (f32) {
         hipLaunchKernelGGL((k_gram_lds_b<NP, WAVES, true>), grid, dim3(WAVES * 64), 0, s, c.insts, c.tasks,
                            c.partials, pass, final_gram);
-    else
+    } else {
         hipLaunchKernelGGL((k_gram_lds_b<NP, WAVES, false>), grid, dim3(WAVES * 64), 0, s, c.insts, c.tasks,
                            c.partials, pass, final_gram);
+    }
     prof_after(s);
 }
 
