@@ -127,12 +127,25 @@ __device__ double power_lambda_regs(const double *G, int S, int n, double *v)
     double lam = 0.0;
     for (int it = 0; it < 100; ++it) {
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        // the iterate is read from LDS eight entries ahead of its use
+        constexpr int CK = NP < 8 ? NP : 8;
+        double vb[2][CK];
 #pragma unroll
-        for (int k = 0; k + 4 <= NP; k += 4) {
-            a0 = __builtin_fma(g[k], v[k], a0);
-            a1 = __builtin_fma(g[k + 1], v[k + 1], a1);
-            a2 = __builtin_fma(g[k + 2], v[k + 2], a2);
-            a3 = __builtin_fma(g[k + 3], v[k + 3], a3);
+        for (int u = 0; u < CK; ++u) vb[0][u] = v[u];
+#pragma unroll
+        for (int k0 = 0; k0 < NP; k0 += CK) {
+            const int cur = (k0 / CK) & 1;
+            if (k0 + CK < NP) {
+#pragma unroll
+                for (int u = 0; u < CK; ++u) vb[cur ^ 1][u] = v[k0 + CK + u];
+            }
+#pragma unroll
+            for (int u = 0; u < CK; u += 4) {
+                a0 = __builtin_fma(g[k0 + u], vb[cur][u], a0);
+                a1 = __builtin_fma(g[k0 + u + 1], vb[cur][u + 1], a1);
+                a2 = __builtin_fma(g[k0 + u + 2], vb[cur][u + 2], a2);
+                a3 = __builtin_fma(g[k0 + u + 3], vb[cur][u + 3], a3);
+            }
         }
         const double y = (a0 + a1) + (a2 + a3);
         const double vy = wave_sum_dpp(vi * y);
@@ -151,19 +164,21 @@ __device__ double power_lambda_regs(const double *G, int S, int n, double *v)
 }
 
 // Upper Cholesky of G + sI for NP <= 64 by the first wave, right-looking with the trailing
-// columns in registers: lane l keeps rows j.. of column l (c[0] = entry (j, l)).  Step j takes
-// the pivot radicand from lane j, r_jj = sqrt, r_jl = c[0] / r_jj, writes row j of R into G,
+// columns in registers: lane l keeps column l, in blocks of 16 rows whose register positions are
+// fixed within a block (the rows shift down by 16 between blocks).  Step j takes the pivot
+// radicand from lane j, r_jj = sqrt, r_jl = (entry (j, l)) / r_jj, writes row j of R into G,
 // broadcasts it through rb (2 NP doubles, upper half zero) and subtracts r_jk r_jl from every
-// remaining entry (k, l) while shifting the rows down by one.  Each entry therefore receives
+// remaining entry (k, l).  Each entry therefore receives
 // exactly the subtractions a_kl - r_0k r_0l - r_1k r_1l - ... in increasing order followed by
 // one division, as in the textbook algorithm.  Entries below the diagonal are not meaningful and
 // are never read.  Returns 0 or 1 + the column whose radicand was <= 0 or not finite.
 template <int NP>
-__device__ int chol_wave_regs(double *G, int S, int n, double s, double *rb)
+__device__ __forceinline__ int chol_wave_regs(double *G, int S, int n, double s, double *rb)
 {
-    static_assert(NP <= 64, "one column per lane");
+    static_assert(NP <= 64 && NP % 16 == 0, "one column per lane, 16-row blocks");
     const int l = threadIdx.x & 63;
     const int col = l < NP ? l : NP - 1;
+    // block J of 16 steps: c[k] = entry (16 J + k, l); the rows shift down by 16 between blocks
     double c[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
@@ -174,26 +189,33 @@ __device__ int chol_wave_regs(double *G, int S, int n, double s, double *rb)
     for (int i = 0; i < 2 * NP; i += 64)
         if (i + l < 2 * NP) rb[i + l] = 0.0;
     wave_sync_c();
-    for (int j = 0; j < n; ++j) {
-        const double d = readlane_d(c[0], j);
-        if (!(d > 0.0) || !isfinite(d)) return j + 1;
-        const double rjj = sqrt(d);
-        const double r = (l == j) ? rjj : c[0] / rjj;
-        if (l < NP) {
-            G[j * S + l] = r;
-            rb[l] = r;
-        }
-        wave_sync_c();
-        const double *rr = rb + j + 1;
-        // only rows below n matter: chunks of 16 rows past n - 1 - j are skipped
+    for (int J = 0; 16 * J < n; ++J) {
+        const double *rr = rb + 16 * J;
 #pragma unroll
-        for (int q = 0; q < NP; q += 16) {
-            if (q > 0 && q > n - 2 - j) break;
+        for (int jj = 0; jj < 16; ++jj) {
+            const int j = 16 * J + jj;
+            if (j >= n) break;
+            const double d = readlane_d(c[jj], j);
+            if (!(d > 0.0) || !isfinite(d)) return j + 1;
+            const double rjj = sqrt(d);
+            const double r = (l == j) ? rjj : c[jj] / rjj;
+            if (l < NP) {
+                G[j * S + l] = r;
+                rb[l] = r;
+            }
+            wave_sync_c();
+            // rows below n only: 16-row chunks past n - 1 are skipped
 #pragma unroll
-            for (int k = q; k < q + 16 && k + 1 < NP; ++k) c[k] = __builtin_fma(-rr[k], r, c[k + 1]);
+            for (int q = 0; q < NP / 16; ++q) {
+                if (q > 0 && 16 * J + 16 * q >= n) break;
+#pragma unroll
+                for (int k = (16 * q > jj + 1 ? 16 * q : jj + 1); k < 16 * q + 16; ++k)
+                    c[k] = __builtin_fma(-rr[k], r, c[k]);
+            }
+            wave_sync_c();
         }
-        c[NP - 1] = 0.0;
-        wave_sync_c();
+#pragma unroll
+        for (int k = 0; k < NP; ++k) c[k] = (k + 16 < NP) ? c[k + 16] : 0.0;
     }
     return 0;
 }
@@ -261,7 +283,7 @@ __device__ double power_lambda_wave(const double *G, int S, int n, double *v)
 
 // Whole-block wrapper: wave 0 iterates, the result is broadcast through LDS.
 template <int NP>
-__device__ double power_lambda(const double *G, int S, int n, double *v, double *red)
+__device__ __forceinline__ double power_lambda(const double *G, int S, int n, double *v, double *red)
 {
     __syncthreads();
     if (threadIdx.x < 64) {
@@ -335,7 +357,7 @@ __device__ int chol_columns(double *G, int S, int n, double s, double *dd)
 }
 
 template <int NP>
-__device__ int chol_inplace(double *G, int S, int n, double s, double *red, double *dd)
+__device__ __forceinline__ int chol_inplace(double *G, int S, int n, double s, double *red, double *dd)
 {
     if constexpr (NP <= 64) {
         __syncthreads();
@@ -437,6 +459,7 @@ __device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const
 
     // norm estimate used by a shift of this pass
     auto norm_estimate = [&]() -> double {
+        const double *Gn = G;
         if (obl_first) {
             // ||X||_2 of (eq:finds2B) is the Euclidean norm: Gram X^T X assembled in w.Ge
             assemble<NP>(w, n, E, false, w.Ge, S);
@@ -445,10 +468,11 @@ __device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const
                 for (int i = threadIdx.x; i < n; i += blockDim.x) t2 += w.Ge[i * S + i];
                 return block_sum(t2, red);
             }
-            return power_lambda<NP>(w.Ge, S, n, vbuf, red);
+            Gn = w.Ge;
+        } else if (sp.shift_mode == SCQR_SHIFT_FRO) {
+            return tr;
         }
-        if (sp.shift_mode == SCQR_SHIFT_FRO) return tr;
-        return power_lambda<NP>(G, S, n, vbuf, red);
+        return power_lambda<NP>(Gn, S, n, vbuf, red);
     };
     double bfac = 1.0;
     if (obl_first) {
@@ -467,37 +491,39 @@ __device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const
     const bool shift_first =
         f32pass || (pass == 1 && (sp.schedule == SCQR_SCHED_FIXED3 || sp.schedule == SCQR_SCHED_ADAPTIVE));
     const bool forced = (sp.force_bd == pass) && variant == 0;
+    // First attempt: shifted (Algorithm 3's first pass, FP32-first) or unshifted.  An unshifted
+    // attempt that breaks down under the ADAPTIVE / ITERATED schedules is retried once with the
+    // shift of this pass (Algorithm 2).  The Cholesky appears once so that it is inlined once.
+    const bool may_retry = sp.schedule == SCQR_SCHED_ADAPTIVE || sp.schedule == SCQR_SCHED_ITERATED;
     int shifted = 0, bd = 0;
     double s = 0.0, nrm = 0.0;
-    if (shift_first) {
-        nrm = norm_estimate();
-        s = shift_value(sp, p.m, n, nrm, bfac, oblique, f32pass);
-        if (sp.zero_shift) s = 0.0;
-        if (f32pass && s > 0.01 * nrm) {
-            bd = -1;  // binary32 shift too large: redo the first pass in binary64
-        } else {
-            bd = forced ? 1 : chol_inplace<NP>(G, S, n, s, red, ybuf);
-        }
-        if (f32pass && bd != 0) {
-            if (threadIdx.x == 0) {
-                ctl->redo_fp64 = 1;
-                info->fell_back_fp64 = 1;
-            }
-            return;
-        }
-        shifted = 1;
-    } else {
-        bd = forced ? 1 : chol_inplace<NP>(G, S, n, 0.0, red, ybuf);
-        if (bd != 0 && (sp.schedule == SCQR_SCHED_ADAPTIVE || sp.schedule == SCQR_SCHED_ITERATED)) {
-            if (threadIdx.x == 0) info->breakdown_mask |= bit;
-            __syncthreads();
-            assemble<NP>(w, n, 0, false, G, S);
+    bool try_shift = shift_first;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if (try_shift) {
             nrm = norm_estimate();
-            s = shift_value(sp, p.m, n, nrm, bfac, oblique, false);
+            s = shift_value(sp, p.m, n, nrm, bfac, oblique, f32pass);
             if (sp.zero_shift) s = 0.0;
             shifted = 1;
-            bd = chol_inplace<NP>(G, S, n, s, red, ybuf);
+            if (f32pass && s > 0.01 * nrm) {
+                bd = -1;  // binary32 shift too large: redo the first pass in binary64
+                break;
+            }
+        } else {
+            s = 0.0;
         }
+        bd = (forced && attempt == 0) ? 1 : chol_inplace<NP>(G, S, n, s, red, ybuf);
+        if (bd == 0 || try_shift || !may_retry) break;
+        if (threadIdx.x == 0) info->breakdown_mask |= bit;
+        __syncthreads();
+        assemble<NP>(w, n, 0, false, G, S);
+        try_shift = true;
+    }
+    if (f32pass && bd != 0) {
+        if (threadIdx.x == 0) {
+            ctl->redo_fp64 = 1;
+            info->fell_back_fp64 = 1;
+        }
+        return;
     }
     if (threadIdx.x == 0) {
         info->shift[pass - 1] = s;
