@@ -78,7 +78,8 @@ scqr_status check_opts(const scqr_opts *o)
 struct Layout {
     int np, nwg, nlvl2;
     int64_t elems;
-    size_t off_ctl, off_G, off_Ge, off_Rt, off_dinv, off_R0, off_R1, off_part, off_lvl2, off_gsum, off_cnt, off_bmax, total;
+    size_t off_ctl, off_G, off_Ge, off_Rt, off_dinv, off_R0, off_R1, off_part, off_lvl2, off_gsum, off_cnt, off_bmax,
+        off_split, total;
 };
 
 Layout layout(int64_t m, int64_t n, bool oblique)
@@ -114,6 +115,8 @@ Layout layout(int64_t m, int64_t n, bool oblique)
     o += align256(sizeof(uint32_t) * (size_t)((L.elems + 255) / 256));
     L.off_bmax = o;
     o += align256(sizeof(double) * (size_t)L.nwg);
+    L.off_split = o;
+    if (L.np == 256) o += align256(sizeof(double) * (2 * 128 * 128 + 2 * 128));
     L.total = o;
     return L;
 }
@@ -134,6 +137,7 @@ Work carve(void *ws, const Layout &L)
     w.gsum = reinterpret_cast<double *>(c + L.off_gsum);
     w.counters = reinterpret_cast<uint32_t *>(c + L.off_cnt);
     w.bmax = reinterpret_cast<double *>(c + L.off_bmax);
+    w.Rsplit = L.np == 256 ? reinterpret_cast<double *>(c + L.off_split) : nullptr;
     w.nwg = L.nwg;
     w.nlvl2 = L.nlvl2;
     w.parts_elems = L.elems;

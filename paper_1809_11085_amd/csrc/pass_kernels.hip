@@ -561,27 +561,31 @@ k_pass_wide_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__
 //        off_k x_{k+1}.
 //   EUC: with OBL, also X^T X (second half of the partial) and the workgroup's Gershgorin
 //        maximum of B (for the first-pass shift of equation (eq:finds2B)).
-//   F32: binary32 MFMA over each 64-row panel, added to the binary64 tiles after the panel.
+//   F32: binary32 MFMA over each panel (64 rows; 32 for n = 256), added to the binary64 tiles
+//        after the panel.
 //   BATCH: workgroup b takes task b of the device task table; otherwise workgroup b takes a
 //        contiguous share of the problem's panels.
 template <int NP, bool OBL, bool EUC, bool F32, bool BATCH>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(NP == 256 ? 512 : 256)
 k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
             const Ctl *__restrict__ ctl, int pass, int final_gram,
             const BatchInst *__restrict__ insts, const BatchTask *__restrict__ tasks)
 {
-    constexpr int PR = 64;
+    constexpr int WV = NP == 256 ? 8 : 4;  // waves
+    constexpr int NTH = 64 * WV;
+    static_assert(!(NP == 256 && OBL), "the n = 256 B-Gram uses k_gram_lds");
+    constexpr int PR = NP == 256 ? 32 : 64;  // rows per panel
     constexpr int H = OBL ? 1 : 0;
     constexpr int NT = NP / 16;
     constexpr int T = NT * (NT + 1) / 2;
-    constexpr int TPW = (T + 3) / 4;
+    constexpr int TPW = (T + WV - 1) / WV;
     constexpr int S = NP + 2;
-    constexpr int PP = PR * NP / 2 / 256;  // double pairs per thread per panel
+    constexpr int PP = PR * NP / 2 / NTH;  // double pairs per thread per panel
     constexpr int64_t E = (int64_t)T * 256;
     __shared__ __attribute__((aligned(16))) double xs[(PR + 2 * H) * S];
     __shared__ __attribute__((aligned(16))) double ys[OBL ? PR * S : 1];
     __shared__ double cs[OBL ? 3 * PR : 1];
-    __shared__ double gm[EUC ? 256 : 1];
+    __shared__ double gm[EUC ? NTH : 1];
 
     int64_t p0, p1;
     if constexpr (BATCH) {
@@ -622,7 +626,7 @@ k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
         int I = 0, J = 0;
-        tile_ij(NT, wv + 4 * u < T ? wv + 4 * u : 0, I, J);
+        tile_ij(NT, wv + WV * u < T ? wv + WV * u : 0, I, J);
         ti[u] = 16 * I;
         tj[u] = 16 * J;
     }
@@ -642,7 +646,7 @@ k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
         const int64_t rb = pnl * PR;
 #pragma unroll
         for (int i = 0; i < PP; ++i) {
-            const int e2 = t + 256 * i;
+            const int e2 = t + NTH * i;
             pre[i] = pair_at(rb + e2 / (NP / 2), 2 * (e2 % (NP / 2)));
         }
         if (OBL) {
@@ -666,7 +670,7 @@ k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
         __syncthreads();  // the previous panel is no longer read
 #pragma unroll
         for (int i = 0; i < PP; ++i) {
-            const int e2 = t + 256 * i;
+            const int e2 = t + NTH * i;
             *reinterpret_cast<double2 *>(xs + (H + e2 / (NP / 2)) * S + 2 * (e2 % (NP / 2))) = pre[i];
         }
         if (OBL) {
@@ -707,7 +711,7 @@ k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
             const double *yr = ysrc + 4 * s4 * S;
 #pragma unroll
             for (int u = 0; u < TPW; ++u) {
-                if (wv + 4 * u < T) {
+                if (wv + WV * u < T) {
                     const double a = xr[ti[u]];
                     const double b = yr[tj[u]];
                     if (F32)
@@ -733,7 +737,7 @@ k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
     double *out = partials + (int64_t)blockIdx.x * (EUC ? 2 * E : E);
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
-        const int tt = wv + u * 4;
+        const int tt = wv + u * WV;
         if (tt < T) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -747,10 +751,128 @@ k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
         __syncthreads();
         if (t == 0) {
             double g = 0.0;
-            for (int i = 0; i < 256; ++i) g = gm[i] > g ? gm[i] : g;
+            for (int i = 0; i < NTH; ++i) g = gm[i] > g ? gm[i] : g;
             bmax[blockIdx.x] = g;
         }
     }
+}
+
+// ------------------------------------------------------------------------------------------
+// Tall-skinny product with a small right factor on FP64 MFMA:
+//   Out[:, c0 + j] = Base[:, c0 + j] + SIGN * sum_{k < K} A[:, k] B[k, c0 + j],  j < NB,
+// for the column block c0 = NB * blockIdx.y (columns at or beyond ncols are not written).  The
+// workgroup stages its K x NB block of B once in LDS in the MFMA B-operand layout (TRANS: B is
+// read transposed, B[k][j] = Bm[j][k]) and streams 32-row panels of A through LDS, the next
+// panel's loads issued before the current panel's MFMAs.  Wave w owns the 16x16 output tiles
+// t = w, w + 4, ... of a panel (2 row groups x NB/16 column groups).  Base may equal Out (each
+// element is read before it is written by the same lane); A must not overlap Out.  Predicated on
+// the control block like the pass kernels (gate).
+template <int K, int NB, bool TRANS, int SIGN>
+__global__ void __launch_bounds__(256)
+k_mm(int64_t m, int ncols, int ka, const double *__restrict__ A, int64_t lda, const double *__restrict__ Bm,
+     int64_t ldb, const double *Base, int64_t ldbase, double *Out, int64_t ldo, const Ctl *__restrict__ ctl,
+     int pass)
+{
+    constexpr int PR = 32;
+    constexpr int SA = K + 2;
+    constexpr int KS = K / 4;          // MFMA k-steps
+    constexpr int CB = NB / 16;        // column groups
+    constexpr int TILES = 2 * CB;      // output tiles per panel
+    constexpr int TPW = (TILES + 3) / 4;
+    constexpr int PP = PR * K / 2 / 256;  // A pairs per thread per panel
+    static_assert(PP >= 1 && (PR * K / 2) % 256 == 0, "panel must split over the workgroup");
+    __shared__ __attribute__((aligned(16))) double as[PR * SA];
+    __shared__ double bs[KS * CB * 64];
+    if (!gate(ctl, pass)) return;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int c0 = NB * blockIdx.y;
+
+    // B block in the B-operand layout: entry (s, cg, l) = B[4 s + l / 16][c0 + 16 cg + l % 16]
+    for (int idx = t; idx < KS * CB * 64; idx += 256) {
+        const int l = idx & 63, cg = (idx >> 6) % CB, s4 = idx / (64 * CB);
+        const int k = 4 * s4 + (l >> 4), j = c0 + 16 * cg + (l & 15);
+        double v = 0.0;
+        if (k < ka && j < ncols) v = TRANS ? as_cview(Bm)[(int64_t)j * ldb + k] : as_cview(Bm)[(int64_t)k * ldb + j];
+        bs[idx] = v;
+    }
+
+    const int64_t npanels = (m + PR - 1) / PR;
+    const int64_t per = (npanels + gridDim.x - 1) / gridDim.x;
+    int64_t p0 = (int64_t)blockIdx.x * per;
+    const int64_t p1 = (p0 + per < npanels) ? p0 + per : npanels;
+    if (p0 > p1) p0 = p1;
+
+    double2 pre[PP];
+    auto load_panel = [&](int64_t pnl) {
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int e2 = t + 256 * i;
+            const int r = e2 / (K / 2), c = 2 * (e2 % (K / 2));
+            const int64_t row = pnl * PR + r;
+            double a = 0.0, b = 0.0;
+            if (row < m) {
+                const gview<const double> src = as_global(A) + row * lda + c;
+                if (c < ka) a = src[0];
+                if (c + 1 < ka) b = src[1];
+            }
+            pre[i] = make_double2(a, b);
+        }
+    };
+    // tiles of this wave: row group rg, column group cg
+    int trg[TPW], tcg[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int tt = wv + 4 * u;
+        trg[u] = tt < TILES ? tt / CB : 0;
+        tcg[u] = tt < TILES ? tt % CB : 0;
+    }
+    if (p0 < p1) load_panel(p0);
+    for (int64_t pn = p0; pn < p1; ++pn) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int e2 = t + 256 * i;
+            *reinterpret_cast<double2 *>(as + (e2 / (K / 2)) * SA + 2 * (e2 % (K / 2))) = pre[i];
+        }
+        __syncthreads();
+        if (pn + 1 < p1) load_panel(pn + 1);
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            if (wv + 4 * u >= TILES) continue;
+            d4 d = (d4){0.0, 0.0, 0.0, 0.0};
+            const double *arow = as + (16 * trg[u] + (lane & 15)) * SA + (lane >> 4);
+            const double *bcol = bs + tcg[u] * 64 + lane;
+#pragma unroll 8
+            for (int s4 = 0; s4 < KS; ++s4)
+                d = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[4 * s4], bcol[s4 * CB * 64], d, 0, 0, 0);
+            // element (i, j) = (lane / 16 + 4 r, lane % 16) of the tile
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = pn * PR + 16 * trg[u] + (lane >> 4) + 4 * r;
+                const int col = c0 + 16 * tcg[u] + (lane & 15);
+                if (row < m && col < ncols) {
+                    const double b0 = Base ? as_global(Base)[row * ldbase + col] : 0.0;
+                    as_global(Out)[row * ldo + col] = SIGN > 0 ? b0 + d[r] : b0 - d[r];
+                }
+            }
+        }
+    }
+}
+
+// The diagonal 128 x 128 blocks of a 256-wide factor (identity padding kept) and their
+// reciprocal diagonals, copied to the stride-128 slots the 128-wide substitution reads:
+// Rsplit = [R~_11 | R~_22 | 1/diag(R~_11) | 1/diag(R~_22)].
+__global__ void __launch_bounds__(256)
+k_split256(const double *__restrict__ Rt, const double *__restrict__ dinv, double *__restrict__ Rsplit,
+           const Ctl *__restrict__ ctl, int pass)
+{
+    if (!gate(ctl, pass)) return;
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < 2 * 128 * 128; e += gridDim.x * 256) {
+        const int b = e >> 14, i = (e >> 7) & 127, j = e & 127;
+        Rsplit[e] = Rt[(128 * b + i) * 256 + 128 * b + j];
+    }
+    if (blockIdx.x == 0) Rsplit[2 * 128 * 128 + threadIdx.x] = dinv[threadIdx.x];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1212,9 +1334,18 @@ template <int NP>
 static hipError_t launch_gram_wide(hipStream_t s, const Problem &p, const Work &w, int pass, bool f32,
                                    bool obl, bool euc, int final_gram)
 {
-    dim3 grid(w.nwg), block(256);
+    dim3 grid(w.nwg), block(NP == 256 ? 512 : 256);
     const BatchInst *ni = nullptr;
     const BatchTask *nt = nullptr;
+    if constexpr (NP == 256) {
+        if (f32)
+            hipLaunchKernelGGL((k_gram_wide<NP, false, false, true, false>), grid, block, 0, s, p, w.partials,
+                               w.bmax, w.ctl, pass, final_gram, ni, nt);
+        else
+            hipLaunchKernelGGL((k_gram_wide<NP, false, false, false, false>), grid, block, 0, s, p, w.partials,
+                               w.bmax, w.ctl, pass, final_gram, ni, nt);
+        return hipGetLastError();
+    } else {
     if (obl && euc)
         hipLaunchKernelGGL((k_gram_wide<NP, true, true, false, false>), grid, block, 0, s, p, w.partials, w.bmax,
                            w.ctl, pass, final_gram, ni, nt);
@@ -1228,6 +1359,43 @@ static hipError_t launch_gram_wide(hipStream_t s, const Problem &p, const Work &
         hipLaunchKernelGGL((k_gram_wide<NP, false, false, false, false>), grid, block, 0, s, p, w.partials, w.bmax,
                            w.ctl, pass, final_gram, ni, nt);
     return hipGetLastError();
+    }
+}
+
+// n = 256 substitution Q = X R~^{-1} as a 2 x 2 block solve, still row-wise in blocked order:
+// Q_1 = X_1 R~_11^{-1};  Q_2 = (X_2 - Q_1 R~_12) R~_22^{-1}  (columns 0..127 and 128..n-1).
+static hipError_t launch_trsm_256(hipStream_t s, const Problem &p, const Work &w, int pass)
+{
+    const double *Rt = factor_of(w, 256, pass), *dv = dinv_of(w, 256, pass);
+    hipLaunchKernelGGL(k_split256, dim3(16), dim3(256), 0, s, Rt, dv, w.Rsplit, w.ctl, pass);
+    const double *R11 = w.Rsplit, *R22 = w.Rsplit + 128 * 128;
+    const double *d11 = w.Rsplit + 2 * 128 * 128, *d22 = d11 + 128;
+    const bool vec = (reinterpret_cast<uintptr_t>(p.X) & 15) == 0 && (p.ldx & 1) == 0 &&
+                     (reinterpret_cast<uintptr_t>(p.Q) & 15) == 0 && (p.ldq & 1) == 0 && (p.n & 1) == 0;
+    const int cus = cu_count();
+    Problem p1 = p;
+    p1.n = 128;
+    p1.np = 128;
+    dim3 grid((unsigned)cus), block(256);
+    if (vec)
+        hipLaunchKernelGGL((k_pass_wide<128, 2, true>), grid, block, 0, s, p1, p1.Q, R11, d11, w.partials, w.ctl, pass, 0);
+    else
+        hipLaunchKernelGGL((k_pass_wide<128, 2, false>), grid, block, 0, s, p1, p1.Q, R11, d11, w.partials, w.ctl, pass, 0);
+    const int n2 = p.n - 128;
+    hipLaunchKernelGGL((k_mm<128, 64, false, -1>), dim3((unsigned)cus, 2), block, 0, s, p.m, n2, 128,
+                       (const double *)p.Q, p.ldq, Rt + 128, (int64_t)256, p.X + 128, p.ldx, p.Q + 128, p.ldq,
+                       w.ctl, pass);
+    Problem p3 = p;
+    p3.n = n2;
+    p3.np = 128;
+    p3.X = p.Q + 128;
+    p3.ldx = p.ldq;
+    p3.Q = p.Q + 128;
+    if (vec)
+        hipLaunchKernelGGL((k_pass_wide<128, 2, true>), grid, block, 0, s, p3, p3.Q, R22, d22, w.partials, w.ctl, pass, 0);
+    else
+        hipLaunchKernelGGL((k_pass_wide<128, 2, false>), grid, block, 0, s, p3, p3.Q, R22, d22, w.partials, w.ctl, pass, 0);
+    return hipGetLastError();
 }
 
 static hipError_t gram_generic(hipStream_t s, const Problem &p, const Work &w, int pass, bool f32,
@@ -1238,7 +1406,9 @@ static hipError_t gram_generic(hipStream_t s, const Problem &p, const Work &w, i
     case 32: return launch_gram_wide<32>(s, p, w, pass, f32, obl, euc, final_gram);
     case 64: return launch_gram_wide<64>(s, p, w, pass, f32, obl, euc, final_gram);
     case 128: return launch_gram_wide<128>(s, p, w, pass, f32, obl, euc, final_gram);
-    case 256: return launch_gram_lds<256, 8>(s, p, w, pass, f32, obl, euc, final_gram);
+    case 256:
+        if (!obl) return launch_gram_wide<256>(s, p, w, pass, f32, obl, euc, final_gram);
+        return launch_gram_lds<256, 8>(s, p, w, pass, f32, obl, euc, final_gram);
     }
     return hipErrorInvalidValue;
 }
@@ -1274,7 +1444,7 @@ hipError_t launch_pass(hipStream_t s, const Problem &p, const Work &w, int mode,
         case 32: e = launch_small<32>(s, p, w, 2, pass, false, 0); break;
         case 64: e = launch_small<64>(s, p, w, 2, pass, false, 0); break;
         case 128: e = launch_wide<128>(s, p, w, 2, pass, 0); break;
-        case 256: e = launch_trsm_big<256>(s, p, w, pass); break;
+        case 256: e = launch_trsm_256(s, p, w, pass); break;
         default: e = hipErrorInvalidValue;
         }
         prof_after(s);
