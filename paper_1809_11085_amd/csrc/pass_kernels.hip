@@ -46,7 +46,8 @@ __device__ __forceinline__ void wave_sync()
 // Each q_ij is thus x_ij minus the products q_ik r_kj, k < j, divided by r_jj: a row-wise
 // substitution in blocked order, whose backward error is bounded row by row as in (eq:backward2).
 // The solved panel then feeds the FP64 MFMA Gram (all upper 16x16 tiles in registers).
-//   MODE 0: Gram of X only.  MODE 1: TRSM + Gram.  MODE 2: TRSM only.
+//   MODE 0: Gram of X only.  MODE 1: TRSM + Gram.  MODE 2: TRSM only.  MODE 3: the transposed
+//   solve x R~^T = y row by row (back substitution in blocked order, for the QR adjoint).
 //   F32: Gram in binary32 MFMA, flushed to binary64 after every 64-row chain (MODE 0 only).
 //   VEC: n even, even leading dimensions and 16-byte aligned X, Q (pairs of doubles per access).
 //   PR: rows per panel (32: 8 waves per workgroup, 64: 4 waves).
@@ -116,8 +117,10 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
                 K -= J;
                 ++J;
             }
-            bl[idx] = -(BATCH ? as_cview(Rt)[(16 * K + 4 * s4 + (l >> 4)) * NP + 16 * J + (l & 15)]
-                              : Rt[(16 * K + 4 * s4 + (l >> 4)) * NP + 16 * J + (l & 15)]);
+            // MODE 3 uses the transposed blocks: entry l holds -r[16K + l%16][16J + 4s + l/16]
+            const int e = MODE == 3 ? (16 * K + (l & 15)) * NP + 16 * J + 4 * s4 + (l >> 4)
+                                    : (16 * K + 4 * s4 + (l >> 4)) * NP + 16 * J + (l & 15);
+            bl[idx] = -(BATCH ? as_cview(Rt)[e] : Rt[e]);
         }
         __syncthreads();
     }
@@ -177,6 +180,58 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
             // The opaque zero keeps the diagonal-block loads inside the panel loop (as scalar
             // loads of a 4 KB working set) instead of hoisting them into spilled registers.
             const int64_t off = pn & (int64_t)p.zero;
+            if constexpr (MODE == 3) {
+                // y = x R~^T solved for x, blocks from the last to the first:
+                //   T_J = Y_J - sum_{K>J} X_K R~_JK^T  (FP64 MFMA),
+                //   x_k = t_k / r_kk, then t_j -= r_jk x_k for j < k (per lane, back substitution)
+#pragma unroll
+                for (int JB = NT - 1; JB >= 0; --JB) {
+                    if (JB < NT - 1) {
+#pragma unroll
+                        for (int g = 0; g < PR / 16; ++g) {
+                            double *blk = P + (16 * g + lk) * S + 16 * JB + li;
+                            d4 d;
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) d[r] = blk[4 * r * S];
+                            const double *arow = P + (16 * g + li) * S + lk;
+#pragma unroll
+                            for (int J2 = JB + 1; J2 < NT; ++J2) {
+                                const int pi = J2 * (J2 - 1) / 2 + JB;
+#pragma unroll
+                                for (int s4 = 0; s4 < 4; ++s4)
+                                    d = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * J2 + 4 * s4],
+                                                                             bl[(pi * 4 + s4) * 64 + lane], d, 0, 0, 0);
+                            }
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) blk[4 * r * S] = d[r];
+                        }
+                        wave_sync();
+                    }
+                    if (lane < PR) {
+                        double *mr = P + lane * S + 16 * JB;
+                        double t[16];
+#pragma unroll
+                        for (int c = 0; c < 16; c += 2) {
+                            const double2 v = *reinterpret_cast<const double2 *>(mr + c);
+                            t[c] = v.x;
+                            t[c + 1] = v.y;
+                        }
+                        int64_t offk = off;
+#pragma unroll
+                        for (int k = 15; k >= 0; --k) {
+                            if (((15 - k) & 1) == 0) asm volatile("" : "+s"(offk));
+                            const double *Rd = Rt + offk + (16 * JB) * NP + 16 * JB;
+                            const double qk = t[k] * dinv[offk + 16 * JB + k];
+                            t[k] = qk;
+#pragma unroll
+                            for (int j = 0; j < k; ++j) t[j] = __builtin_fma(-qk, Rd[j * NP + k], t[j]);
+                        }
+#pragma unroll
+                        for (int c = 0; c < 16; c += 2) *reinterpret_cast<double2 *>(mr + c) = make_double2(t[c], t[c + 1]);
+                    }
+                    wave_sync();
+                }
+            } else {
             int pi0 = 0;
 #pragma unroll
             for (int J = 0; J < NT; ++J) {
@@ -234,6 +289,7 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
                     for (int c = 0; c < 16; c += 2) *reinterpret_cast<double2 *>(mr + c) = make_double2(t[c], t[c + 1]);
                 }
                 wave_sync();
+            }
             }
             // ---- Q panel -> HBM
 #pragma unroll
@@ -325,7 +381,8 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
 // B-operand layout, diagonal blocks one row per lane with wave-uniform scalar loads), the solved
 // panel is written to Q, and wave w accumulates the upper Gram tiles t = w, w+4, ... over all
 // 64 rows.  The next panel's loads are issued before the current one is solved.
-//   MODE 1: substitution + Gram.  MODE 2: substitution only.
+//   MODE 1: substitution + Gram.  MODE 2: substitution only.  MODE 3: the transposed solve
+//   x R~^T = y (back substitution in blocked order, for the QR adjoint).
 //   The workgroup takes the 64-row panels [p0, p1).
 // Upper Gram tiles t = W, W + WAVES, ... of a PR-row panel (src = panel + (lane/16) S + lane%16),
 // with the tile coordinates known at compile time.
@@ -382,7 +439,9 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
             K -= J;
             ++J;
         }
-        bl[idx] = -as_cview(Rt)[(16 * K + 4 * s4 + (l >> 4)) * NP + 16 * J + (l & 15)];
+        const int e = MODE == 3 ? (16 * K + (l & 15)) * NP + 16 * J + 4 * s4 + (l >> 4)
+                                : (16 * K + 4 * s4 + (l >> 4)) * NP + 16 * J + (l & 15);
+        bl[idx] = -as_cview(Rt)[e];
     }
 
     d4 acc[TPW];
@@ -430,6 +489,52 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
         // ---- substitution of rows 16 wv .. 16 wv + 15
         const int R0 = 16 * wv;
         const int64_t off = pn & (int64_t)p.zero;
+        if constexpr (MODE == 3) {
+#pragma unroll
+            for (int JB = NT - 1; JB >= 0; --JB) {
+                if (JB < NT - 1) {
+                    double *blk = P + (R0 + lk) * S + 16 * JB + li;
+                    d4 d;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) d[r] = blk[4 * r * S];
+                    const double *arow = P + (R0 + li) * S + lk;
+#pragma unroll
+                    for (int J2 = JB + 1; J2 < NT; ++J2) {
+                        const int pi = J2 * (J2 - 1) / 2 + JB;
+#pragma unroll
+                        for (int s4 = 0; s4 < 4; ++s4)
+                            d = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * J2 + 4 * s4], bl[(pi * 4 + s4) * 64 + lane],
+                                                                     d, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) blk[4 * r * S] = d[r];
+                    wave_sync();
+                }
+                if (lane < 16) {
+                    double *mr = P + (R0 + lane) * S + 16 * JB;
+                    double t[16];
+#pragma unroll
+                    for (int c = 0; c < 16; c += 2) {
+                        const double2 v = *reinterpret_cast<const double2 *>(mr + c);
+                        t[c] = v.x;
+                        t[c + 1] = v.y;
+                    }
+                    int64_t offk = off;
+#pragma unroll
+                    for (int k = 15; k >= 0; --k) {
+                        if (((15 - k) & 1) == 0) asm volatile("" : "+s"(offk));
+                        const cview<double> Rd = as_cview(Rt) + offk + (16 * JB) * NP + 16 * JB;
+                        const double qk = t[k] * as_cview(dinv)[offk + 16 * JB + k];
+                        t[k] = qk;
+#pragma unroll
+                        for (int j = 0; j < k; ++j) t[j] = __builtin_fma(-qk, Rd[j * NP + k], t[j]);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 16; c += 2) *reinterpret_cast<double2 *>(mr + c) = make_double2(t[c], t[c + 1]);
+                }
+                wave_sync();
+            }
+        } else {
         int pi0 = 0;
 #pragma unroll
         for (int J = 0; J < NT; ++J) {
@@ -474,6 +579,7 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
                 for (int c = 0; c < 16; c += 2) *reinterpret_cast<double2 *>(mr + c) = make_double2(t[c], t[c + 1]);
             }
             wave_sync();
+        }
         }
         __syncthreads();
 
@@ -1566,6 +1672,105 @@ hipError_t launch_reduce_b(hipStream_t s, const BatchClass &c, int pass, int fin
     prof_before(s, "b_reduce");
     hipLaunchKernelGGL(k_reduce_b, grid, block, 0, s, c.insts, c.partials, elems, pass, final_gram);
     prof_after(s);
+    return hipGetLastError();
+}
+
+// ---- products and transposed solves used by the QR adjoint ---------------------------------
+// Out = Base + SIGN * A B (TRANS: B read transposed), K the padded width of the factor.
+template <int K, int NB, bool TRANS, int SIGN>
+static void launch_mm_t(hipStream_t s, int64_t m, int ncols, int ka, const double *A, int64_t lda, const double *B,
+                        int64_t ldb, const double *Base, int64_t ldbase, double *Out, int64_t ldo)
+{
+    const int cus = cu_count();
+    int64_t panels = (m + 31) / 32;
+    int64_t gx = panels < 2 * (int64_t)cus ? panels : 2 * (int64_t)cus;
+    if (gx < 1) gx = 1;
+    dim3 grid((unsigned)gx, (unsigned)((ncols + NB - 1) / NB)), block(256);
+    hipLaunchKernelGGL((k_mm<K, NB, TRANS, SIGN>), grid, block, 0, s, m, ncols, ka, A, lda, B, ldb, Base, ldbase,
+                       Out, ldo, (const Ctl *)nullptr, 0);
+}
+
+hipError_t launch_mm(hipStream_t s, int np, int64_t m, int ncols, int ka, const double *A, int64_t lda,
+                     const double *B, int64_t ldb, const double *Base, int64_t ldbase, double *Out, int64_t ldo)
+{
+    switch (np) {
+    case 16: launch_mm_t<16, 16, false, 1>(s, m, ncols, ka, A, lda, B, ldb, Base, ldbase, Out, ldo); break;
+    case 32: launch_mm_t<32, 32, false, 1>(s, m, ncols, ka, A, lda, B, ldb, Base, ldbase, Out, ldo); break;
+    case 64: launch_mm_t<64, 64, false, 1>(s, m, ncols, ka, A, lda, B, ldb, Base, ldbase, Out, ldo); break;
+    case 128: launch_mm_t<128, 64, false, 1>(s, m, ncols, ka, A, lda, B, ldb, Base, ldbase, Out, ldo); break;
+    case 256: launch_mm_t<256, 32, false, 1>(s, m, ncols, ka, A, lda, B, ldb, Base, ldbase, Out, ldo); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int NP>
+static void launch_solve_tile(hipStream_t s, const Problem &p, const double *Rp, const double *dinv, bool vec)
+{
+    const Ctl *nc = nullptr;
+    const BatchInst *ni = nullptr;
+    const BatchTask *nt = nullptr;
+    double *np_ = nullptr;
+    dim3 grid(pass_grid(p.m, NP)), block(512);
+    if (vec)
+        hipLaunchKernelGGL((k_pass_tile<NP, 3, false, true, kPanelRows, false>), grid, block, 0, s, p, p.Q, Rp, dinv,
+                           np_, nc, 0, 0, ni, nt);
+    else
+        hipLaunchKernelGGL((k_pass_tile<NP, 3, false, false, kPanelRows, false>), grid, block, 0, s, p, p.Q, Rp,
+                           dinv, np_, nc, 0, 0, ni, nt);
+}
+
+static void launch_solve_wide(hipStream_t s, const Problem &p, const double *Rp, const double *dinv, bool vec)
+{
+    const Ctl *nc = nullptr;
+    double *np_ = nullptr;
+    dim3 grid((unsigned)cu_count()), block(256);
+    if (vec)
+        hipLaunchKernelGGL((k_pass_wide<128, 3, true>), grid, block, 0, s, p, p.Q, Rp, dinv, np_, nc, 0, 0);
+    else
+        hipLaunchKernelGGL((k_pass_wide<128, 3, false>), grid, block, 0, s, p, p.Q, Rp, dinv, np_, nc, 0, 0);
+}
+
+// Y <- X with X R~^T = Y, in place (row-major m x n, padded factor Rp of width np with identity
+// padding, reciprocal diagonal dinv).  n = 256 is a 2 x 2 block solve:
+// X_2 = Y_2 R~_22^{-T},  X_1 = (Y_1 - X_2 R~_12^T) R~_11^{-T}.
+hipError_t launch_solve_t(hipStream_t s, int np, int64_t m, int n, double *Y, int64_t ldy, const double *Rp,
+                          const double *dinv, double *Rsplit)
+{
+    Problem p{};
+    p.m = m;
+    p.n = n;
+    p.np = np;
+    p.X = Y;
+    p.ldx = ldy;
+    p.Q = Y;
+    p.ldq = ldy;
+    const bool vec = (reinterpret_cast<uintptr_t>(Y) & 15) == 0 && (ldy & 1) == 0 && (n & 1) == 0;
+    switch (np) {
+    case 16: launch_solve_tile<16>(s, p, Rp, dinv, vec); break;
+    case 32: launch_solve_tile<32>(s, p, Rp, dinv, vec); break;
+    case 64: launch_solve_tile<64>(s, p, Rp, dinv, vec); break;
+    case 128: launch_solve_wide(s, p, Rp, dinv, vec); break;
+    case 256: {
+        hipLaunchKernelGGL(k_split256, dim3(16), dim3(256), 0, s, Rp, dinv, Rsplit, (const Ctl *)nullptr, 0);
+        const double *R11 = Rsplit, *R22 = Rsplit + 128 * 128;
+        const double *d11 = Rsplit + 2 * 128 * 128, *d22 = d11 + 128;
+        const int n2 = n - 128;
+        Problem p2 = p;
+        p2.n = n2;
+        p2.np = 128;
+        p2.X = Y + 128;
+        p2.Q = Y + 128;
+        launch_solve_wide(s, p2, R22, d22, vec);
+        launch_mm_t<128, 64, true, -1>(s, m, 128, n2, Y + 128, ldy, Rp + 128, 256, Y, ldy, Y, ldy);
+        Problem p1 = p;
+        p1.n = 128;
+        p1.np = 128;
+        launch_solve_wide(s, p1, R11, d11, vec);
+        break;
+    }
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -212,6 +212,13 @@ hipError_t launch_final_omega(hipStream_t s, const Problem &p, const Work &w,
 hipError_t launch_finalize_r(hipStream_t s, const Problem &p, const Work &w);
 
 // QR adjoint
+// Out = Base + A B for the padded width np (Base may be null or equal Out; A must not overlap Out).
+hipError_t launch_mm(hipStream_t s, int np, int64_t m, int ncols, int ka, const double *A, int64_t lda,
+                     const double *B, int64_t ldb, const double *Base, int64_t ldbase, double *Out, int64_t ldo);
+// Y <- X with X R~^T = Y in place; Rp is the np x np factor with identity padding, Rsplit scratch
+// of 2 * 128 * 128 + 256 doubles for np = 256.
+hipError_t launch_solve_t(hipStream_t s, int np, int64_t m, int n, double *Y, int64_t ldy, const double *Rp,
+                          const double *dinv, double *Rsplit);
 hipError_t launch_backward(hipStream_t s, int64_t m, int n, const double *Q, int64_t ldq,
                            const double *R, int64_t ldr, const double *dQ, int64_t lddq,
                            const double *dR, int64_t lddr, double *dX, int64_t lddx, void *ws);
