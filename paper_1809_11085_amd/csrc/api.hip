@@ -416,7 +416,7 @@ scqr_status scqr_qr(void *stream, int64_t m, int64_t n, const double *X, int64_t
         if (e == hipSuccess) e = launch_reduce(s, w, pass, E, fg);
         if (e == hipSuccess && pass < P) e = launch_chol(s, p, w, sp, pass + 1, 0);
     }
-    if (e == hipSuccess) e = launch_finalize_r(s, p, w);
+    if (e == hipSuccess) e = launch_finalize_r(s, p, w, P);
     if (e == hipSuccess && fg) e = launch_final_omega(s, p, w, sp);
     return hip_status(e);
 }

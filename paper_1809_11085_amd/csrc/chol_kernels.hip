@@ -111,7 +111,7 @@ __device__ __forceinline__ double wave_sum_dpp(double v)
 }
 
 // Power iteration of the first wave for NP <= 64 with row i of G held in lane i's registers
-// and the iterate broadcast from LDS (same rule and start vector as power_lambda_wave).
+// and the iterate broadcast from LDS (the stopping rule and start vector of power_lambda).
 template <int NP>
 __device__ double power_lambda_regs(const double *G, int S, int n, double *v)
 {
@@ -220,84 +220,98 @@ __device__ __forceinline__ int chol_wave_regs(double *G, int S, int n, double s,
     return 0;
 }
 
-// Rayleigh-quotient power iteration for lambda_max of the symmetric n x n matrix G (stride S),
-// run by the first wave alone (no workgroup barriers): start vector 1/sqrt(n), at most 100
-// iterations, stop when the quotient changes by <= 1e-6 relative (the stopping rule of the normest
-// estimator the paper names).  The quotient is a lower
-// bound of lambda_max.  Returns the same value in every lane of wave 0.
+// Power iteration for NP = 128 / 256 by the whole workgroup (same start vector, stopping rule and
+// iteration cap as power_lambda).  NP = 128: threads 2i and 2i + 1 hold the two halves of
+// row i in registers; NP = 256: thread i streams row i from G.  The iterate is broadcast from LDS;
+// the two sums per iteration are reduced in a fixed order (DPP within each wave, then the four
+// wave sums in order), so every thread holds the same values.
 template <int NP>
-__device__ double power_lambda_wave(const double *G, int S, int n, double *v)
+__device__ double power_lambda_block(const double *G, int S, int n, double *v, double *red)
 {
-    constexpr int C = (NP + 63) / 64;
-    const int lane = threadIdx.x & 63;
-    double vv[C];
+    static_assert(NP == 128 || NP == 256, "block power iteration");
+    constexpr int H = NP == 128 ? 2 : 1;       // threads per row
+    constexpr int CW = NP / H;                 // columns per thread
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int row = t / H, h = t % H;
+    const bool act = row < n;
+    double g[NP == 128 ? CW : 1];
+    if constexpr (NP == 128) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const int i = lane + 64 * c;
-        vv[c] = (i < n) ? 1.0 / sqrt((double)n) : 0.0;
-        if (i < NP) v[i] = vv[c];
+        for (int k = 0; k < CW; ++k) g[k] = (act && CW * h + k < n) ? G[row * S + CW * h + k] : 0.0;
     }
-    wave_sync_c();
-    double lam = 0.0;
+    const double v0 = act ? 1.0 / sqrt((double)n) : 0.0;
+    if (h == 0) v[row] = v0;
+    __syncthreads();
+    double vi = v0, lam = 0.0;
     for (int it = 0; it < 100; ++it) {
-        double y[C], vy = 0.0, yy = 0.0;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        if constexpr (NP == 128) {
+            const double *vv = v + CW * h;
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int i = lane + 64 * c;
-            double acc = 0.0;
-            if (i < n) {
-                const double *gi = G + i * S;
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                int k = 0;
-                for (; k + 4 <= n; k += 4) {
-                    a0 = __builtin_fma(gi[k], v[k], a0);
-                    a1 = __builtin_fma(gi[k + 1], v[k + 1], a1);
-                    a2 = __builtin_fma(gi[k + 2], v[k + 2], a2);
-                    a3 = __builtin_fma(gi[k + 3], v[k + 3], a3);
-                }
-                for (; k < n; ++k) a0 = __builtin_fma(gi[k], v[k], a0);
-                acc = (a0 + a1) + (a2 + a3);
+            for (int k = 0; k < CW; k += 4) {
+                a0 = __builtin_fma(g[k], vv[k], a0);
+                a1 = __builtin_fma(g[k + 1], vv[k + 1], a1);
+                a2 = __builtin_fma(g[k + 2], vv[k + 2], a2);
+                a3 = __builtin_fma(g[k + 3], vv[k + 3], a3);
             }
-            y[c] = acc;
-            vy += vv[c] * acc;
-            yy += acc * acc;
+        } else {
+            const double *gr = G + (act ? row : 0) * S;
+            for (int k0 = 0; k0 < NP; k0 += 16) {
+                double gb[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) gb[u] = (act && k0 + u < n) ? gr[k0 + u] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 16; u += 4) {
+                    a0 = __builtin_fma(gb[u], v[k0 + u], a0);
+                    a1 = __builtin_fma(gb[u + 1], v[k0 + u + 1], a1);
+                    a2 = __builtin_fma(gb[u + 2], v[k0 + u + 2], a2);
+                    a3 = __builtin_fma(gb[u + 3], v[k0 + u + 3], a3);
+                }
+            }
         }
-        vy = wave_sum(vy);
-        yy = wave_sum(yy);
+        double y = (a0 + a1) + (a2 + a3);
+        if constexpr (H == 2) y = y + dpp_d<0xB1>(y);  // the two halves of the row (quad xor 1)
+        const double cvy = (h == 0) ? vi * y : 0.0, cyy = (h == 0) ? y * y : 0.0;
+        const double svy = wave_sum_dpp(cvy), syy = wave_sum_dpp(cyy);
+        __syncthreads();  // everyone has read v and red
+        if (lane == 0) {
+            red[2 * wv] = svy;
+            red[2 * wv + 1] = syy;
+        }
+        __syncthreads();
+        const double vy = (red[0] + red[2]) + (red[4] + red[6]);
+        const double yy = (red[1] + red[3]) + (red[5] + red[7]);
         const double prev = lam;
         lam = vy;
         if (!(yy > 0.0)) break;
-        const double inv = 1.0 / sqrt(yy);
-        wave_sync_c();
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int i = lane + 64 * c;
-            vv[c] = y[c] * inv;
-            if (i < NP) v[i] = vv[c];
-        }
-        wave_sync_c();
+        vi = y * (1.0 / sqrt(yy));
+        if (h == 0 && row < NP) v[row] = vi;
+        __syncthreads();
         if (it > 0 && fabs(lam - prev) <= 1e-6 * fabs(lam)) break;
     }
+    __syncthreads();
     return lam;
 }
 
-// Whole-block wrapper: wave 0 iterates, the result is broadcast through LDS.
+// ||X||_2^2 estimate (normest's rule: Rayleigh-quotient power iteration on the Gram from the
+// start vector 1/sqrt(n), stopped at a relative change <= 1e-6 or after 100 iterations; a lower
+// bound of lambda_max).  NP <= 64: the first wave alone, the result broadcast through LDS.
 template <int NP>
 __device__ __forceinline__ double power_lambda(const double *G, int S, int n, double *v, double *red)
 {
     __syncthreads();
-    if (threadIdx.x < 64) {
-        double lam;
-        if constexpr (NP <= 64)
-            lam = power_lambda_regs<NP>(G, S, n, v);
-        else
-            lam = power_lambda_wave<NP>(G, S, n, v);
-        if (threadIdx.x == 0) red[15] = lam;
+    if constexpr (NP >= 128) {
+        return power_lambda_block<NP>(G, S, n, v, red);
+    } else {
+        if (threadIdx.x < 64) {
+            const double lam = power_lambda_regs<NP>(G, S, n, v);
+            if (threadIdx.x == 0) red[15] = lam;
+        }
+        __syncthreads();
+        const double lam = red[15];
+        __syncthreads();
+        return lam;
     }
-    __syncthreads();
-    const double lam = red[15];
-    __syncthreads();
-    return lam;
 }
 
 // In-place upper Cholesky of G + sI (upper triangle of G, stride S), one column per thread
@@ -356,6 +370,106 @@ __device__ int chol_columns(double *G, int S, int n, double s, double *dd)
     return 0;
 }
 
+// Blocked right-looking upper Cholesky of G + sI for NP >= 128 by the whole workgroup, in
+// 16-column blocks J: (1) the first wave factors the 16 x 16 diagonal block in registers (one
+// column per lane, pivot rows broadcast with readlane), (2) one thread per column solves the
+// block row R_J,K = R_JJ^{-T} A_J,K by forward substitution (multiplying by the reciprocals of
+// the diagonal), (3) the upper tiles of the trailing
+// matrix receive A_KL -= R_J,K^T R_J,L on FP64 MFMA (a 16-row Gram of the block row).  Every
+// entry is reduced by all earlier rows before its own block is factored, as in the textbook
+// algorithm; only the grouping of the subtractions differs (by blocks of 16 rows).  Returns 0 or
+// 1 + the column whose radicand was <= 0 or not finite.
+template <int NP>
+__device__ __forceinline__ int chol_blocked(double *G, int S, int n, double s, double *red, double *dd)
+{
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int i = t; i < n; i += kCholThreads) G[i * S + i] += s;
+    __syncthreads();
+    const int nb = (n + 15) / 16;
+    for (int J = 0; J < nb; ++J) {
+        const int j0 = 16 * J;
+        const int w = n - j0 < 16 ? n - j0 : 16;
+        // (1) diagonal block
+        if (wv == 0) {
+            const int col = j0 + (li < w ? li : 0);
+            double c[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) c[k] = (k < w) ? G[(j0 + k) * S + col] : 0.0;
+            int bd = 0;
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                if (jj >= w) break;
+                const double d = readlane_d(c[jj], jj);
+                if (!(d > 0.0) || !isfinite(d)) {
+                    bd = j0 + jj + 1;
+                    break;
+                }
+                const double rjj = sqrt(d);
+                const double r = (li == jj) ? rjj : c[jj] / rjj;
+#pragma unroll
+                for (int k = jj + 1; k < 16; ++k) c[k] = __builtin_fma(-readlane_d(r, k), r, c[k]);
+                c[jj] = r;
+            }
+            if (bd == 0 && lane < w) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    if (k <= lane) G[(j0 + k) * S + j0 + lane] = c[k];
+                    if (k == lane) dd[lane] = 1.0 / c[k];  // reciprocal of r_{j0 + lane, j0 + lane}
+                }
+            }
+            if (lane == 0) red[13] = (double)bd;
+        }
+        __syncthreads();
+        const int bd = (int)red[13];
+        if (bd) return bd;
+        // (2) block row: r_{j, col} = (a_{j, col} - sum_{i < j} r_{i j} r_{i, col}) / r_jj
+        for (int col = j0 + 16 + t; col < n; col += kCholThreads) {
+            double a[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) a[k] = (k < w) ? G[(j0 + k) * S + col] : 0.0;
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                if (jj >= w) break;
+                double v = a[jj];
+#pragma unroll
+                for (int i = 0; i < jj; ++i) v = __builtin_fma(-G[(j0 + i) * S + j0 + jj], a[i], v);
+                a[jj] = v * dd[jj];
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (k < w) G[(j0 + k) * S + col] = a[k];
+        }
+        __syncthreads();
+        // (3) trailing upper tiles (K, L), J < K <= L < nb, tile index enumerated row by row
+        const int nr = nb - J - 1;
+        const int ntile = nr * (nr + 1) / 2;
+        for (int tt = wv; tt < ntile; tt += kCholThreads / 64) {
+            int K = 0, rem = tt;
+            while (rem >= nr - K) {
+                rem -= nr - K;
+                ++K;
+            }
+            const int L = K + rem;
+            const int k0 = 16 * (J + 1 + K), l0 = 16 * (J + 1 + L);
+            d4 d;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) d[r] = G[(k0 + lk + 4 * r) * S + l0 + li];
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int row = j0 + 4 * s4 + lk;
+                const double av = row < n ? -G[row * S + k0 + li] : 0.0;
+                const double bv = row < n ? G[row * S + l0 + li] : 0.0;
+                d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) G[(k0 + lk + 4 * r) * S + l0 + li] = d[r];
+        }
+        __syncthreads();
+    }
+    return 0;
+}
+
 template <int NP>
 __device__ __forceinline__ int chol_inplace(double *G, int S, int n, double s, double *red, double *dd)
 {
@@ -372,7 +486,7 @@ __device__ __forceinline__ int chol_inplace(double *G, int S, int n, double s, d
         return bd;
     }
     __syncthreads();
-    return chol_columns<false>(G, S, n, s, dd);
+    return chol_blocked<NP>(G, S, n, s, red, dd);
 }
 
 __device__ double shift_value(const SchedParams &sp, int64_t m, int n, double norm2sq,
@@ -914,6 +1028,20 @@ __global__ void __launch_bounds__(256) k_finalize_r(Problem p, Work w)
         finalize_big<NP>(p, w);
 }
 
+// NP = 256 after launch_rprod256: R from P_passes (the identity when no pass was applied).
+__global__ void __launch_bounds__(256) k_finalize_copy256(Problem p, Work w)
+{
+    const int passes = w.ctl->pass;
+    const double *src = passes >= 2 ? w.Racc[passes & 1] : w.Rhist;
+    const int n = p.n;
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < n * n; e += gridDim.x * 256) {
+        const int i = e / n, j = e % n;
+        double v = 0.0;
+        if (j >= i) v = passes >= 1 ? src[i * 256 + j] : (i == j ? 1.0 : 0.0);
+        p.R[(int64_t)i * p.ldr + j] = v;
+    }
+}
+
 template <int NP>
 __global__ void __launch_bounds__(256) k_finalize_b(const BatchInst *__restrict__ insts)
 {
@@ -1006,8 +1134,15 @@ hipError_t launch_set_factor(hipStream_t s, const Work &w, int np, int n, const 
     return hipGetLastError();
 }
 
-hipError_t launch_finalize_r(hipStream_t s, const Problem &p, const Work &w)
+hipError_t launch_finalize_r(hipStream_t s, const Problem &p, const Work &w, int maxp)
 {
+    if (p.np == 256) {
+        prof_before(s, "finalize_r");
+        hipError_t e = launch_rprod256(s, w, maxp);
+        if (e == hipSuccess) hipLaunchKernelGGL(k_finalize_copy256, dim3(64), dim3(256), 0, s, p, w);
+        prof_after(s);
+        return e == hipSuccess ? hipGetLastError() : e;
+    }
     prof_before(s, "finalize_r");
     switch (p.np) {
     case 16: hipLaunchKernelGGL((k_finalize_r<16>), dim3(1), dim3(256), 0, s, p, w); break;

@@ -872,12 +872,13 @@ k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
 // panel's loads issued before the current panel's MFMAs.  Wave w owns the 16x16 output tiles
 // t = w, w + 4, ... of a panel (2 row groups x NB/16 column groups).  Base may equal Out (each
 // element is read before it is written by the same lane); A must not overlap Out.  Predicated on
-// the control block like the pass kernels (gate).
+// the control block like the pass kernels (gate), and with min_pass > 0 on at least min_pass
+// passes having been applied.
 template <int K, int NB, bool TRANS, int SIGN>
 __global__ void __launch_bounds__(256)
 k_mm(int64_t m, int ncols, int ka, const double *__restrict__ A, int64_t lda, const double *__restrict__ Bm,
      int64_t ldb, const double *Base, int64_t ldbase, double *Out, int64_t ldo, const Ctl *__restrict__ ctl,
-     int pass)
+     int pass, int min_pass)
 {
     constexpr int PR = 32;
     constexpr int SA = K + 2;
@@ -890,6 +891,7 @@ k_mm(int64_t m, int ncols, int ka, const double *__restrict__ A, int64_t lda, co
     __shared__ __attribute__((aligned(16))) double as[PR * SA];
     __shared__ double bs[KS * CB * 64];
     if (!gate(ctl, pass)) return;
+    if (min_pass > 0 && ctl->pass < min_pass) return;
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int c0 = NB * blockIdx.y;
@@ -1490,7 +1492,7 @@ static hipError_t launch_trsm_256(hipStream_t s, const Problem &p, const Work &w
     const int n2 = p.n - 128;
     hipLaunchKernelGGL((k_mm<128, 64, false, -1>), dim3((unsigned)cus, 2), block, 0, s, p.m, n2, 128,
                        (const double *)p.Q, p.ldq, Rt + 128, (int64_t)256, p.X + 128, p.ldx, p.Q + 128, p.ldq,
-                       w.ctl, pass);
+                       w.ctl, pass, 0);
     Problem p3 = p;
     p3.n = n2;
     p3.np = 128;
@@ -1687,7 +1689,7 @@ static void launch_mm_t(hipStream_t s, int64_t m, int ncols, int ka, const doubl
     if (gx < 1) gx = 1;
     dim3 grid((unsigned)gx, (unsigned)((ncols + NB - 1) / NB)), block(256);
     hipLaunchKernelGGL((k_mm<K, NB, TRANS, SIGN>), grid, block, 0, s, m, ncols, ka, A, lda, B, ldb, Base, ldbase,
-                       Out, ldo, (const Ctl *)nullptr, 0);
+                       Out, ldo, (const Ctl *)nullptr, 0, 0);
 }
 
 hipError_t launch_mm(hipStream_t s, int np, int64_t m, int ncols, int ka, const double *A, int64_t lda,
@@ -1770,6 +1772,21 @@ hipError_t launch_solve_t(hipStream_t s, int np, int64_t m, int n, double *Y, in
         break;
     }
     default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// R = R~_q ... R~_1 for a 256-wide factor: product q (2 <= q <= maxp) is P_q = R~_q P_{q-1} into
+// Racc[q % 2] (P_1 = R~_1), launched for every q and skipped on the device beyond the applied
+// passes.
+hipError_t launch_rprod256(hipStream_t s, const Work &w, int maxp)
+{
+    for (int q = 2; q <= maxp; ++q) {
+        const double *A = w.Rhist + (int64_t)(q - 1) * 256 * 256;
+        const double *B = q == 2 ? w.Rhist : w.Racc[(q - 1) & 1];
+        hipLaunchKernelGGL((k_mm<256, 32, false, 1>), dim3(8, 8), dim3(256), 0, s, (int64_t)256, 256, 256, A,
+                           (int64_t)256, B, (int64_t)256, (const double *)nullptr, (int64_t)256, w.Racc[q & 1],
+                           (int64_t)256, w.ctl, 0, q);
     }
     return hipGetLastError();
 }
