@@ -1028,8 +1028,9 @@ __global__ void __launch_bounds__(256) k_finalize_r(Problem p, Work w)
         finalize_big<NP>(p, w);
 }
 
-// NP = 256 after launch_rprod256: R from P_passes (the identity when no pass was applied).
-__global__ void __launch_bounds__(256) k_finalize_copy256(Problem p, Work w)
+// NP = 128 / 256 after launch_rprod: R from P_passes (the identity when no pass was applied).
+template <int NP>
+__global__ void __launch_bounds__(256) k_finalize_copy(Problem p, Work w)
 {
     const int passes = w.ctl->pass;
     const double *src = passes >= 2 ? w.Racc[passes & 1] : w.Rhist;
@@ -1037,7 +1038,7 @@ __global__ void __launch_bounds__(256) k_finalize_copy256(Problem p, Work w)
     for (int e = blockIdx.x * 256 + threadIdx.x; e < n * n; e += gridDim.x * 256) {
         const int i = e / n, j = e % n;
         double v = 0.0;
-        if (j >= i) v = passes >= 1 ? src[i * 256 + j] : (i == j ? 1.0 : 0.0);
+        if (j >= i) v = passes >= 1 ? src[i * NP + j] : (i == j ? 1.0 : 0.0);
         p.R[(int64_t)i * p.ldr + j] = v;
     }
 }
@@ -1136,10 +1137,15 @@ hipError_t launch_set_factor(hipStream_t s, const Work &w, int np, int n, const 
 
 hipError_t launch_finalize_r(hipStream_t s, const Problem &p, const Work &w, int maxp)
 {
-    if (p.np == 256) {
+    if (p.np >= 128) {
         prof_before(s, "finalize_r");
-        hipError_t e = launch_rprod256(s, w, maxp);
-        if (e == hipSuccess) hipLaunchKernelGGL(k_finalize_copy256, dim3(64), dim3(256), 0, s, p, w);
+        hipError_t e = launch_rprod(s, w, p.np, maxp);
+        if (e == hipSuccess) {
+            if (p.np == 256)
+                hipLaunchKernelGGL((k_finalize_copy<256>), dim3(64), dim3(256), 0, s, p, w);
+            else
+                hipLaunchKernelGGL((k_finalize_copy<128>), dim3(64), dim3(256), 0, s, p, w);
+        }
         prof_after(s);
         return e == hipSuccess ? hipGetLastError() : e;
     }

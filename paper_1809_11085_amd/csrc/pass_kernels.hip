@@ -866,10 +866,14 @@ k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
 // ------------------------------------------------------------------------------------------
 // Tall-skinny product with a small right factor on FP64 MFMA:
 //   Out[:, c0 + j] = Base[:, c0 + j] + SIGN * sum_{k < K} A[:, k] B[k, c0 + j],  j < NB,
-// for the column block c0 = NB * blockIdx.y (columns at or beyond ncols are not written).  The
-// workgroup stages its K x NB block of B once in LDS in the MFMA B-operand layout (TRANS: B is
-// read transposed, B[k][j] = Bm[j][k]) and streams 32-row panels of A through LDS, the next
-// panel's loads issued before the current panel's MFMAs.  Wave w owns the 16x16 output tiles
+// over column blocks of NB columns (columns at or beyond ncols are not written).  The grid is
+// (panel groups) x (column blocks); when the number of groups is a multiple of 8 the dispatch
+// order is remapped so that the column blocks of one panel group are consecutive workgroups of
+// one XCD (dispatch goes round-robin over the 8 XCDs): they run together and share the XCD's L2
+// for A, which HBM then delivers once instead of once per column block.  The workgroup stages
+// its K x NB block of B once in LDS in the MFMA B-operand layout (TRANS: B is read transposed,
+// B[k][j] = Bm[j][k]) and streams 32-row panels of A through LDS, the next panel's loads issued
+// before the current panel's MFMAs.  Wave w owns the 16x16 output tiles
 // t = w, w + 4, ... of a panel (2 row groups x NB/16 column groups).  Base may equal Out (each
 // element is read before it is written by the same lane); A must not overlap Out.  Predicated on
 // the control block like the pass kernels (gate), and with min_pass > 0 on at least min_pass
@@ -894,7 +898,14 @@ k_mm(int64_t m, int ncols, int ka, const double *__restrict__ A, int64_t lda, co
     if (min_pass > 0 && ctl->pass < min_pass) return;
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int c0 = NB * blockIdx.y;
+    const int ngrp = gridDim.x, ncb = gridDim.y;
+    int grp = blockIdx.x, cb = blockIdx.y;
+    if ((ngrp & 7) == 0) {
+        const int b = blockIdx.x + ngrp * blockIdx.y, j = b >> 3;
+        cb = j % ncb;
+        grp = (j / ncb) * 8 + (b & 7);
+    }
+    const int c0 = NB * cb;
 
     // B block in the B-operand layout: entry (s, cg, l) = B[4 s + l / 16][c0 + 16 cg + l % 16]
     for (int idx = t; idx < KS * CB * 64; idx += 256) {
@@ -906,8 +917,8 @@ k_mm(int64_t m, int ncols, int ka, const double *__restrict__ A, int64_t lda, co
     }
 
     const int64_t npanels = (m + PR - 1) / PR;
-    const int64_t per = (npanels + gridDim.x - 1) / gridDim.x;
-    int64_t p0 = (int64_t)blockIdx.x * per;
+    const int64_t per = (npanels + ngrp - 1) / ngrp;
+    int64_t p0 = (int64_t)grp * per;
     const int64_t p1 = (p0 + per < npanels) ? p0 + per : npanels;
     if (p0 > p1) p0 = p1;
 
@@ -1776,17 +1787,22 @@ hipError_t launch_solve_t(hipStream_t s, int np, int64_t m, int n, double *Y, in
     return hipGetLastError();
 }
 
-// R = R~_q ... R~_1 for a 256-wide factor: product q (2 <= q <= maxp) is P_q = R~_q P_{q-1} into
-// Racc[q % 2] (P_1 = R~_1), launched for every q and skipped on the device beyond the applied
-// passes.
-hipError_t launch_rprod256(hipStream_t s, const Work &w, int maxp)
+// R = R~_q ... R~_1 for a factor of padded width np = 128 or 256: product q (2 <= q <= maxp) is
+// P_q = R~_q P_{q-1} into Racc[q % 2] (P_1 = R~_1), launched for every q and skipped on the device
+// beyond the applied passes.
+hipError_t launch_rprod(hipStream_t s, const Work &w, int np, int maxp)
 {
     for (int q = 2; q <= maxp; ++q) {
-        const double *A = w.Rhist + (int64_t)(q - 1) * 256 * 256;
+        const double *A = w.Rhist + (int64_t)(q - 1) * np * np;
         const double *B = q == 2 ? w.Rhist : w.Racc[(q - 1) & 1];
-        hipLaunchKernelGGL((k_mm<256, 32, false, 1>), dim3(8, 8), dim3(256), 0, s, (int64_t)256, 256, 256, A,
-                           (int64_t)256, B, (int64_t)256, (const double *)nullptr, (int64_t)256, w.Racc[q & 1],
-                           (int64_t)256, w.ctl, 0, q);
+        if (np == 256)
+            hipLaunchKernelGGL((k_mm<256, 32, false, 1>), dim3(8, 8), dim3(256), 0, s, (int64_t)256, 256, 256, A,
+                               (int64_t)256, B, (int64_t)256, (const double *)nullptr, (int64_t)256, w.Racc[q & 1],
+                               (int64_t)256, w.ctl, 0, q);
+        else
+            hipLaunchKernelGGL((k_mm<128, 64, false, 1>), dim3(4, 2), dim3(256), 0, s, (int64_t)128, 128, 128, A,
+                               (int64_t)128, B, (int64_t)128, (const double *)nullptr, (int64_t)128, w.Racc[q & 1],
+                               (int64_t)128, w.ctl, 0, q);
     }
     return hipGetLastError();
 }

@@ -211,7 +211,7 @@ hipError_t launch_final_omega(hipStream_t s, const Problem &p, const Work &w,
                               const SchedParams &sp);
 // maxp: the most passes the schedule can apply (the n = 256 product is one launch per pass).
 hipError_t launch_finalize_r(hipStream_t s, const Problem &p, const Work &w, int maxp);
-hipError_t launch_rprod256(hipStream_t s, const Work &w, int maxp);
+hipError_t launch_rprod(hipStream_t s, const Work &w, int np, int maxp);
 
 // QR adjoint
 // Out = Base + A B for the padded width np (Base may be null or equal Out; A must not overlap Out).
