@@ -376,14 +376,36 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
 
 // ------------------------------------------------------------------------------------------
 // Fused pass for 64 < n <= 128 (NP = 128).  A workgroup of 4 waves shares one 64-row panel in
-// LDS.  Each wave solves its own 16 rows by the same blocked row-wise substitution as the
-// n <= 64 kernel (off-diagonal 16x16 blocks on FP64 MFMA against -R~_KJ held in LDS in the
-// B-operand layout, diagonal blocks one row per lane with wave-uniform scalar loads), the solved
-// panel is written to Q, and wave w accumulates the upper Gram tiles t = w, w+4, ... over all
-// 64 rows.  The next panel's loads are issued before the current one is solved.
+// LDS.  Each wave solves its own 16 rows block by block: the off-diagonal 16x16 blocks on FP64
+// MFMA against -R~_KJ held in LDS in the B-operand layout, then the diagonal block in the MFMA
+// result layout with all 64 lanes (row broadcasts by DPP, per-lane coefficients r_kj / r_kk from
+// an LDS table; diag_solve_steps).  The solved panel is written to Q, and wave w accumulates
+// the upper Gram tiles t = w, w+4, ... over all 64 rows.  The next panel's loads are issued before the current one is solved.
 //   MODE 1: substitution + Gram.  MODE 2: substitution only.  MODE 3: the transposed solve
 //   x R~^T = y (back substitution in blocked order, for the QR adjoint).
 //   The workgroup takes the 64-row panels [p0, p1).
+// Lane K of every 16-lane row of the wave, broadcast to the whole row (DPP row_newbcast; every
+// lane is written, so the old value is never used).
+template <int K>
+__device__ __forceinline__ double row_bcast(double v)
+{
+    return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + K, 0xF, 0xF, true);
+}
+
+// Substitution inside a 16 x 16 diagonal block held in the MFMA result layout (lane l holds
+// column l % 16 of rows l / 16 + 4 r): column K's value is final when step K runs; it is
+// broadcast along the lane's row and column j takes -t_K c[K] (c = r_Kj / r_KK for the columns
+// K still updates, 0 elsewhere).  FWD runs K = 0, 1, ..., 15, otherwise K = 15, ..., 0.  The
+// reciprocal diagonal is applied by the caller after the last step.
+template <int K, bool FWD>
+__device__ __forceinline__ void diag_solve_steps(d4 &d, const double (&c)[16])
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r) d[r] = __builtin_fma(-row_bcast<K>(d[r]), c[K], d[r]);
+    if constexpr (FWD && K < 15) diag_solve_steps<K + 1, FWD>(d, c);
+    if constexpr (!FWD && K > 0) diag_solve_steps<K - 1, FWD>(d, c);
+}
+
 // Upper Gram tiles t = W, W + WAVES, ... of a PR-row panel (src = panel + (lane/16) S + lane%16),
 // with the tile coordinates known at compile time.
 template <int NP, int W, int WAVES, int TPW, int PR, int S>
@@ -424,6 +446,7 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
     constexpr int PP = PR * NP / 2 / (WAVES * 64);  // double pairs per thread per panel
     __shared__ __attribute__((aligned(16))) double P[PR * S];
     __shared__ double bl[NOFF * 4 * 64];
+    __shared__ double dtab[NT * 256 + NP];
 
     if (!gate(ctl, pass)) return;
     const bool want_gram = MODE == 1 && gram_needed(ctl, pass, final_gram);
@@ -443,6 +466,18 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
                                 : (16 * K + 4 * s4 + (l >> 4)) * NP + 16 * J + (l & 15);
         bl[idx] = -as_cview(Rt)[e];
     }
+    // Diagonal-block coefficients, entry (J, k, j): forward r_kj / r_kk for k < j, transposed
+    // (MODE 3) r_jk / r_kk for j < k, zero elsewhere; then the reciprocal diagonal.
+    for (int idx = threadIdx.x; idx < NT * 256; idx += WAVES * 64) {
+        const int J = idx >> 8, k = (idx >> 4) & 15, j = idx & 15;
+        double v = 0.0;
+        if (MODE == 3 ? j < k : k < j) {
+            const int e = MODE == 3 ? (16 * J + j) * NP + 16 * J + k : (16 * J + k) * NP + 16 * J + j;
+            v = as_cview(Rt)[e] * as_cview(dinv)[16 * J + k];
+        }
+        dtab[idx] = v;
+    }
+    for (int i = threadIdx.x; i < NP; i += WAVES * 64) dtab[NT * 256 + i] = as_cview(dinv)[i];
 
     d4 acc[TPW];
 #pragma unroll
@@ -486,100 +521,46 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
         __syncthreads();
         if (pn + 1 < p1) load_panel(pn + 1);
 
-        // ---- substitution of rows 16 wv .. 16 wv + 15
+        // ---- substitution of rows 16 wv .. 16 wv + 15, block by block: the block's MFMA update
+        // from the solved blocks, then the diagonal solve in the result layout
         const int R0 = 16 * wv;
-        const int64_t off = pn & (int64_t)p.zero;
-        if constexpr (MODE == 3) {
 #pragma unroll
-            for (int JB = NT - 1; JB >= 0; --JB) {
-                if (JB < NT - 1) {
-                    double *blk = P + (R0 + lk) * S + 16 * JB + li;
-                    d4 d;
+        for (int it = 0; it < NT; ++it) {
+            const int J = MODE == 3 ? NT - 1 - it : it;
+            double *blk = P + (R0 + lk) * S + 16 * J + li;
+            double cf[16];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) d[r] = blk[4 * r * S];
-                    const double *arow = P + (R0 + li) * S + lk;
+            for (int k = 0; k < 16; ++k) cf[k] = dtab[(J * 16 + k) * 16 + li];
+            const double dj = dtab[NT * 256 + 16 * J + li];
+            d4 d;
 #pragma unroll
-                    for (int J2 = JB + 1; J2 < NT; ++J2) {
-                        const int pi = J2 * (J2 - 1) / 2 + JB;
+            for (int r = 0; r < 4; ++r) d[r] = blk[4 * r * S];
+            const double *arow = P + (R0 + li) * S + lk;
+            if constexpr (MODE == 3) {
+                //   T_J = Y_J - sum_{K>J} X_K R~_JK^T
 #pragma unroll
-                        for (int s4 = 0; s4 < 4; ++s4)
-                            d = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * J2 + 4 * s4], bl[(pi * 4 + s4) * 64 + lane],
-                                                                     d, 0, 0, 0);
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) blk[4 * r * S] = d[r];
-                    wave_sync();
-                }
-                if (lane < 16) {
-                    double *mr = P + (R0 + lane) * S + 16 * JB;
-                    double t[16];
-#pragma unroll
-                    for (int c = 0; c < 16; c += 2) {
-                        const double2 v = *reinterpret_cast<const double2 *>(mr + c);
-                        t[c] = v.x;
-                        t[c + 1] = v.y;
-                    }
-                    int64_t offk = off;
-#pragma unroll
-                    for (int k = 15; k >= 0; --k) {
-                        if (((15 - k) & 1) == 0) asm volatile("" : "+s"(offk));
-                        const cview<double> Rd = as_cview(Rt) + offk + (16 * JB) * NP + 16 * JB;
-                        const double qk = t[k] * as_cview(dinv)[offk + 16 * JB + k];
-                        t[k] = qk;
-#pragma unroll
-                        for (int j = 0; j < k; ++j) t[j] = __builtin_fma(-qk, Rd[j * NP + k], t[j]);
-                    }
-#pragma unroll
-                    for (int c = 0; c < 16; c += 2) *reinterpret_cast<double2 *>(mr + c) = make_double2(t[c], t[c + 1]);
-                }
-                wave_sync();
-            }
-        } else {
-        int pi0 = 0;
-#pragma unroll
-        for (int J = 0; J < NT; ++J) {
-            if (J > 0) {
-                double *blk = P + (R0 + lk) * S + 16 * J + li;
-                d4 d;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) d[r] = blk[4 * r * S];
-                const double *arow = P + (R0 + li) * S + lk;
-                int pi = pi0;
-#pragma unroll
-                for (int K = 0; K < J; ++K, ++pi)
+                for (int J2 = J + 1; J2 < NT; ++J2) {
+                    const int pi = J2 * (J2 - 1) / 2 + J;
 #pragma unroll
                     for (int s4 = 0; s4 < 4; ++s4)
-                        d = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * K + 4 * s4], bl[(pi * 4 + s4) * 64 + lane], d,
+                        d = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * J2 + 4 * s4], bl[(pi * 4 + s4) * 64 + lane], d,
                                                                  0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) blk[4 * r * S] = d[r];
-                pi0 += J;
-                wave_sync();
-            }
-            if (lane < 16) {
-                double *mr = P + (R0 + lane) * S + 16 * J;
-                double t[16];
-#pragma unroll
-                for (int c = 0; c < 16; c += 2) {
-                    const double2 v = *reinterpret_cast<const double2 *>(mr + c);
-                    t[c] = v.x;
-                    t[c + 1] = v.y;
                 }
-                int64_t offk = off;
+                diag_solve_steps<15, false>(d, cf);
+            } else {
+                //   T_J = X_J - sum_{K<J} Q_K R~_KJ
+                const int pi0 = J * (J - 1) / 2;
 #pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    if ((k & 1) == 0) asm volatile("" : "+s"(offk));
-                    const cview<double> Rd = as_cview(Rt) + offk + (16 * J) * NP + 16 * J;
-                    const double qk = t[k] * as_cview(dinv)[offk + 16 * J + k];
-                    t[k] = qk;
+                for (int K = 0; K < J; ++K)
 #pragma unroll
-                    for (int j = k + 1; j < 16; ++j) t[j] = __builtin_fma(-qk, Rd[k * NP + j], t[j]);
-                }
-#pragma unroll
-                for (int c = 0; c < 16; c += 2) *reinterpret_cast<double2 *>(mr + c) = make_double2(t[c], t[c + 1]);
+                    for (int s4 = 0; s4 < 4; ++s4)
+                        d = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * K + 4 * s4], bl[((pi0 + K) * 4 + s4) * 64 + lane],
+                                                                 d, 0, 0, 0);
+                diag_solve_steps<0, true>(d, cf);
             }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) blk[4 * r * S] = d[r] * dj;
             wave_sync();
-        }
         }
         __syncthreads();
 
