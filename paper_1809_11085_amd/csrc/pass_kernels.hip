@@ -855,8 +855,9 @@ k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
 // its K x NB block of B once in LDS in the MFMA B-operand layout (TRANS: B is read transposed,
 // B[k][j] = Bm[j][k]) and streams 32-row panels of A through LDS, the next panel's loads issued
 // before the current panel's MFMAs.  Wave w owns the 16x16 output tiles
-// t = w, w + 4, ... of a panel (2 row groups x NB/16 column groups).  Base may equal Out (each
-// element is read before it is written by the same lane); A must not overlap Out.  Predicated on
+// t = w, w + 4, ... of a panel (2 row groups x NB/16 column groups); its Base elements are
+// loaded with the panel, one panel ahead.  Base may equal Out (each element is read by the lane
+// that writes it, before the write, and panels are disjoint); A must not overlap Out.  Predicated on
 // the control block like the pass kernels (gate), and with min_pass > 0 on at least min_pass
 // passes having been applied.
 template <int K, int NB, bool TRANS, int SIGN>
@@ -903,7 +904,17 @@ k_mm(int64_t m, int ncols, int ka, const double *__restrict__ A, int64_t lda, co
     const int64_t p1 = (p0 + per < npanels) ? p0 + per : npanels;
     if (p0 > p1) p0 = p1;
 
+    // tiles of this wave: row group rg, column group cg
+    int trg[TPW], tcg[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int tt = wv + 4 * u;
+        trg[u] = tt < TILES ? tt / CB : 0;
+        tcg[u] = tt < TILES ? tt % CB : 0;
+    }
+    // A panel pairs and the wave's Base elements of a panel, loaded one panel ahead
     double2 pre[PP];
+    double bpre[TPW][4];
     auto load_panel = [&](int64_t pnl) {
 #pragma unroll
         for (int i = 0; i < PP; ++i) {
@@ -918,15 +929,17 @@ k_mm(int64_t m, int ncols, int ka, const double *__restrict__ A, int64_t lda, co
             }
             pre[i] = make_double2(a, b);
         }
-    };
-    // tiles of this wave: row group rg, column group cg
-    int trg[TPW], tcg[TPW];
 #pragma unroll
-    for (int u = 0; u < TPW; ++u) {
-        const int tt = wv + 4 * u;
-        trg[u] = tt < TILES ? tt / CB : 0;
-        tcg[u] = tt < TILES ? tt % CB : 0;
-    }
+        for (int u = 0; u < TPW; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = pnl * PR + 16 * trg[u] + (lane >> 4) + 4 * r;
+                const int col = c0 + 16 * tcg[u] + (lane & 15);
+                double b0 = 0.0;
+                if (Base && wv + 4 * u < TILES && row < m && col < ncols) b0 = as_global(Base)[row * ldbase + col];
+                bpre[u][r] = b0;
+            }
+    };
     if (p0 < p1) load_panel(p0);
     for (int64_t pn = p0; pn < p1; ++pn) {
         __syncthreads();
@@ -935,6 +948,11 @@ k_mm(int64_t m, int ncols, int ka, const double *__restrict__ A, int64_t lda, co
             const int e2 = t + 256 * i;
             *reinterpret_cast<double2 *>(as + (e2 / (K / 2)) * SA + 2 * (e2 % (K / 2))) = pre[i];
         }
+        double bcur[TPW][4];
+#pragma unroll
+        for (int u = 0; u < TPW; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bcur[u][r] = bpre[u][r];
         __syncthreads();
         if (pn + 1 < p1) load_panel(pn + 1);
 #pragma unroll
@@ -951,10 +969,118 @@ k_mm(int64_t m, int ncols, int ka, const double *__restrict__ A, int64_t lda, co
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = pn * PR + 16 * trg[u] + (lane >> 4) + 4 * r;
                 const int col = c0 + 16 * tcg[u] + (lane & 15);
-                if (row < m && col < ncols) {
-                    const double b0 = Base ? as_global(Base)[row * ldbase + col] : 0.0;
-                    as_global(Out)[row * ldo + col] = SIGN > 0 ? b0 + d[r] : b0 - d[r];
-                }
+                if (row < m && col < ncols) as_global(Out)[row * ldo + col] = SIGN > 0 ? bcur[u][r] + d[r] : bcur[u][r] - d[r];
+            }
+        }
+    }
+}
+
+// The same product for K = 128 / 256 with the right factor in registers: the workgroup owns a
+// 64-column block, wave w the 16 columns c0 + 16 w .. c0 + 16 w + 15, whose K x 16 slice of B it
+// keeps in registers in the MFMA B-operand layout (loaded once).  32-row panels of A are staged
+// in LDS one panel ahead as in k_mm, and each wave computes both 16-row tiles of its columns:
+// one LDS operand read per MFMA and two independent accumulation chains.  Dispatch order, Base
+// and predication as in k_mm.
+template <int K, bool TRANS, int SIGN>
+__global__ void __launch_bounds__(256)
+k_mm_breg(int64_t m, int ncols, int ka, const double *__restrict__ A, int64_t lda, const double *__restrict__ Bm,
+          int64_t ldb, const double *Base, int64_t ldbase, double *Out, int64_t ldo, const Ctl *__restrict__ ctl,
+          int pass, int min_pass)
+{
+    constexpr int PR = 32;
+    constexpr int SA = K + 2;
+    constexpr int KS = K / 4;
+    constexpr int NB = 64;
+    constexpr int PP = PR * K / 2 / 256;
+    static_assert(K == 128 || K == 256, "k_mm_breg serves K = 128 and 256");
+    __shared__ __attribute__((aligned(16))) double as[PR * SA];
+    if (!gate(ctl, pass)) return;
+    if (min_pass > 0 && ctl->pass < min_pass) return;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int ngrp = gridDim.x, ncb = gridDim.y;
+    int grp = blockIdx.x, cb = blockIdx.y;
+    if ((ngrp & 7) == 0) {
+        const int b = blockIdx.x + ngrp * blockIdx.y, j = b >> 3;
+        cb = j % ncb;
+        grp = (j / ncb) * 8 + (b & 7);
+    }
+    const int col = NB * cb + 16 * wv + (lane & 15);
+    const bool colok = col < ncols;
+
+    // B slice: bf[s4] = B[4 s4 + lane / 16][col]
+    double bf[KS];
+#pragma unroll
+    for (int s4 = 0; s4 < KS; ++s4) {
+        const int k = 4 * s4 + (lane >> 4);
+        double v = 0.0;
+        if (colok && k < ka) v = TRANS ? as_global(Bm)[(int64_t)col * ldb + k] : as_global(Bm)[(int64_t)k * ldb + col];
+        bf[s4] = v;
+    }
+
+    const int64_t npanels = (m + PR - 1) / PR;
+    const int64_t per = (npanels + ngrp - 1) / ngrp;
+    int64_t p0 = (int64_t)grp * per;
+    const int64_t p1 = (p0 + per < npanels) ? p0 + per : npanels;
+    if (p0 > p1) p0 = p1;
+
+    double2 pre[PP];
+    double bpre[2][4];
+    auto load_panel = [&](int64_t pnl) {
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int e2 = t + 256 * i;
+            const int r = e2 / (K / 2), c = 2 * (e2 % (K / 2));
+            const int64_t row = pnl * PR + r;
+            double a = 0.0, b = 0.0;
+            if (row < m) {
+                const gview<const double> src = as_global(A) + row * lda + c;
+                if (c < ka) a = src[0];
+                if (c + 1 < ka) b = src[1];
+            }
+            pre[i] = make_double2(a, b);
+        }
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = pnl * PR + 16 * g + (lane >> 4) + 4 * r;
+                double b0 = 0.0;
+                if (Base && colok && row < m) b0 = as_global(Base)[row * ldbase + col];
+                bpre[g][r] = b0;
+            }
+    };
+    if (p0 < p1) load_panel(p0);
+    for (int64_t pn = p0; pn < p1; ++pn) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int e2 = t + 256 * i;
+            *reinterpret_cast<double2 *>(as + (e2 / (K / 2)) * SA + 2 * (e2 % (K / 2))) = pre[i];
+        }
+        double bcur[2][4];
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bcur[g][r] = bpre[g][r];
+        __syncthreads();
+        if (pn + 1 < p1) load_panel(pn + 1);
+
+        d4 acc0 = (d4){0.0, 0.0, 0.0, 0.0}, acc1 = (d4){0.0, 0.0, 0.0, 0.0};
+        const double *a0 = as + (lane & 15) * SA + (lane >> 4);
+        const double *a1 = a0 + 16 * SA;
+#pragma unroll
+        for (int s4 = 0; s4 < KS; ++s4) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[4 * s4], bf[s4], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[4 * s4], bf[s4], acc1, 0, 0, 0);
+        }
+        // element (i, j) = (lane / 16 + 4 r, lane % 16) of tile g
+        if (colok) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row0 = pn * PR + (lane >> 4) + 4 * r, row1 = row0 + 16;
+                if (row0 < m) as_global(Out)[row0 * ldo + col] = SIGN > 0 ? bcur[0][r] + acc0[r] : bcur[0][r] - acc0[r];
+                if (row1 < m) as_global(Out)[row1 * ldo + col] = SIGN > 0 ? bcur[1][r] + acc1[r] : bcur[1][r] - acc1[r];
             }
         }
     }
@@ -1482,7 +1608,7 @@ static hipError_t launch_trsm_256(hipStream_t s, const Problem &p, const Work &w
     else
         hipLaunchKernelGGL((k_pass_wide<128, 2, false>), grid, block, 0, s, p1, p1.Q, R11, d11, w.partials, w.ctl, pass, 0);
     const int n2 = p.n - 128;
-    hipLaunchKernelGGL((k_mm<128, 64, false, -1>), dim3((unsigned)cus, 2), block, 0, s, p.m, n2, 128,
+    hipLaunchKernelGGL((k_mm_breg<128, false, -1>), dim3((unsigned)cus, (unsigned)((n2 + 63) / 64)), block, 0, s, p.m, n2, 128,
                        (const double *)p.Q, p.ldq, Rt + 128, (int64_t)256, p.X + 128, p.ldx, p.Q + 128, p.ldq,
                        w.ctl, pass, 0);
     Problem p3 = p;
@@ -1679,9 +1805,15 @@ static void launch_mm_t(hipStream_t s, int64_t m, int ncols, int ka, const doubl
     int64_t panels = (m + 31) / 32;
     int64_t gx = panels < 2 * (int64_t)cus ? panels : 2 * (int64_t)cus;
     if (gx < 1) gx = 1;
-    dim3 grid((unsigned)gx, (unsigned)((ncols + NB - 1) / NB)), block(256);
-    hipLaunchKernelGGL((k_mm<K, NB, TRANS, SIGN>), grid, block, 0, s, m, ncols, ka, A, lda, B, ldb, Base, ldbase,
-                       Out, ldo, (const Ctl *)nullptr, 0, 0);
+    if constexpr (K >= 128) {
+        dim3 grid((unsigned)gx, (unsigned)((ncols + 63) / 64)), block(256);
+        hipLaunchKernelGGL((k_mm_breg<K, TRANS, SIGN>), grid, block, 0, s, m, ncols, ka, A, lda, B, ldb, Base, ldbase,
+                           Out, ldo, (const Ctl *)nullptr, 0, 0);
+    } else {
+        dim3 grid((unsigned)gx, (unsigned)((ncols + NB - 1) / NB)), block(256);
+        hipLaunchKernelGGL((k_mm<K, NB, TRANS, SIGN>), grid, block, 0, s, m, ncols, ka, A, lda, B, ldb, Base, ldbase,
+                           Out, ldo, (const Ctl *)nullptr, 0, 0);
+    }
 }
 
 hipError_t launch_mm(hipStream_t s, int np, int64_t m, int ncols, int ka, const double *A, int64_t lda,
@@ -1777,11 +1909,11 @@ hipError_t launch_rprod(hipStream_t s, const Work &w, int np, int maxp)
         const double *A = w.Rhist + (int64_t)(q - 1) * np * np;
         const double *B = q == 2 ? w.Rhist : w.Racc[(q - 1) & 1];
         if (np == 256)
-            hipLaunchKernelGGL((k_mm<256, 32, false, 1>), dim3(8, 8), dim3(256), 0, s, (int64_t)256, 256, 256, A,
+            hipLaunchKernelGGL((k_mm_breg<256, false, 1>), dim3(8, 4), dim3(256), 0, s, (int64_t)256, 256, 256, A,
                                (int64_t)256, B, (int64_t)256, (const double *)nullptr, (int64_t)256, w.Racc[q & 1],
                                (int64_t)256, w.ctl, 0, q);
         else
-            hipLaunchKernelGGL((k_mm<128, 64, false, 1>), dim3(4, 2), dim3(256), 0, s, (int64_t)128, 128, 128, A,
+            hipLaunchKernelGGL((k_mm_breg<128, false, 1>), dim3(4, 2), dim3(256), 0, s, (int64_t)128, 128, 128, A,
                                (int64_t)128, B, (int64_t)128, (const double *)nullptr, (int64_t)128, w.Racc[q & 1],
                                (int64_t)128, w.ctl, 0, q);
     }
