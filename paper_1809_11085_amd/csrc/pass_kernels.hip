@@ -408,25 +408,28 @@ __device__ __forceinline__ void diag_solve_steps(d4 &d, const double (&c)[16])
 
 // Upper Gram tiles t = W, W + WAVES, ... of a PR-row panel (src = panel + (lane/16) S + lane%16),
 // with the tile coordinates known at compile time.
+// (the tile coordinates are template constants, so op[] stays in registers without indexing)
+template <int NT, int W, int WAVES, int U, int TPW>
+__device__ __forceinline__ void wide_gram_step(d4 (&acc)[TPW], const double (&op)[NT])
+{
+    constexpr int t = W + U * WAVES;
+    if constexpr (t < NT * (NT + 1) / 2) {
+        constexpr int I = tile_row(NT, t), J = tile_col(NT, t);
+        acc[U] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[I], op[J], acc[U], 0, 0, 0);
+    }
+    if constexpr (U + 1 < TPW) wide_gram_step<NT, W, WAVES, U + 1, TPW>(acc, op);
+}
+
 template <int NP, int W, int WAVES, int TPW, int PR, int S>
 __device__ __forceinline__ void wide_gram(d4 (&acc)[TPW], const double *src)
 {
     constexpr int NT = NP / 16;
-    constexpr int T = NT * (NT + 1) / 2;
     for (int s4 = 0; s4 < PR / 4; ++s4) {
         const double *row = src + 4 * s4 * S;
         double op[NT];
 #pragma unroll
         for (int b = 0; b < NT; ++b) op[b] = row[16 * b];
-#pragma unroll
-        for (int u = 0; u < TPW; ++u) {
-            const int t = W + u * WAVES;
-            if (t < T) {
-                int I = 0, J = 0;
-                tile_ij(NT, t, I, J);
-                acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[I], op[J], acc[u], 0, 0, 0);
-            }
-        }
+        wide_gram_step<NT, W, WAVES, 0, TPW>(acc, op);
     }
 }
 
@@ -1212,6 +1215,14 @@ gram_lds_body(const Problem &p, double *__restrict__ part_out, double *__restric
     }
     double bm = 0.0;
     int chain = 0;
+    // column offsets (16 I, 16 J) of this wave's tiles t = wv + WAVES u
+    int ti[TPW], tj[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int t = wv + u * WAVES < T ? wv + u * WAVES : 0;
+        ti[u] = 16 * tile_row(NT, t);
+        tj[u] = 16 * tile_col(NT, t);
+    }
 
     for (int64_t pn = p0; pn < p1; ++pn) {
         const int64_t r0 = pn * PR;
@@ -1257,14 +1268,12 @@ gram_lds_body(const Problem &p, double *__restrict__ part_out, double *__restric
             for (int u = 0; u < TPW; ++u) {
                 const int t = wv + u * WAVES;
                 if (t < T) {
-                    int I, J;
-                    tile_ij(NT, t, I, J);
-                    const double a = xrow[16 * I];
-                    double b = xrow[16 * J];
+                    const double a = xrow[ti[u]];
+                    double b = xrow[tj[u]];
                     if (OBL) {
                         // (B x)_k, evaluated as off_{k-1} x_{k-1} + diag_k x_k, + off_k x_{k+1}
-                        const double bx = c_lo * xrow[16 * J - S] + c_d * b;
-                        const double by = bx + c_up * xrow[16 * J + S];
+                        const double bx = c_lo * xrow[tj[u] - S] + c_d * b;
+                        const double by = bx + c_up * xrow[tj[u] + S];
                         if (EUC) acce[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acce[u], 0, 0, 0);
                         b = by;
                     }

@@ -20,15 +20,24 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 __host__ __device__ constexpr int upper_tiles(int nt) { return nt * (nt + 1) / 2; }
 
 // Tile t (row-major enumeration of the upper triangle) -> block row I, block column J.
-__host__ __device__ inline void tile_ij(int nt, int t, int &I, int &J)
+__host__ __device__ constexpr int tile_row(int nt, int t)
 {
-    int i = 0, rem = t;
-    while (rem >= nt - i) {
-        rem -= nt - i;
+    int i = 0;
+    while (t >= nt - i) {
+        t -= nt - i;
         ++i;
     }
-    I = i;
-    J = i + rem;
+    return i;
+}
+__host__ __device__ constexpr int tile_col(int nt, int t)
+{
+    const int i = tile_row(nt, t);
+    return t - (i * nt - i * (i - 1) / 2) + i;
+}
+__host__ __device__ inline void tile_ij(int nt, int t, int &I, int &J)
+{
+    I = tile_row(nt, t);
+    J = tile_col(nt, t);
 }
 
 // Element e of a tile in the FP64 MFMA accumulator layout (lane l, register r; stored at
