@@ -371,47 +371,48 @@ __device__ int chol_columns(double *G, int S, int n, double s, double *dd)
 }
 
 // Blocked right-looking upper Cholesky of G + sI for NP >= 128 by the whole workgroup, in
-// 16-column blocks J: (1) the first wave factors the 16 x 16 diagonal block in registers (one
-// column per lane, pivot rows broadcast with readlane), (2) one thread per column solves the
-// block row R_J,K = R_JJ^{-T} A_J,K by forward substitution (multiplying by the reciprocals of
-// the diagonal), (3) the upper tiles of the trailing
-// matrix receive A_KL -= R_J,K^T R_J,L on FP64 MFMA (a 16-row Gram of the block row).  Every
-// entry is reduced by all earlier rows before its own block is factored, as in the textbook
-// algorithm; only the grouping of the subtractions differs (by blocks of 16 rows).  Returns 0 or
-// 1 + the column whose radicand was <= 0 or not finite.
+// 16-column blocks J of the matrix padded to NP with an identity block (rows and columns n..NP-1
+// of the upper triangle; the factor of the padded matrix is diag(R, I), so every block is full
+// and every loop has compile-time bounds): (1) the first wave factors the 16 x 16 diagonal block
+// in registers (one column per lane, pivot rows broadcast with readlane), (2) one thread per
+// column solves the block row R_J,K = R_JJ^{-T} A_J,K by forward substitution (multiplying by the
+// reciprocals of the diagonal), (3) the upper tiles of the trailing matrix receive
+// A_KL -= R_J,K^T R_J,L on FP64 MFMA (a 16-row Gram of the block row).  Every entry is reduced
+// by all earlier rows before its own block is factored, as in the textbook algorithm; only the
+// grouping of the subtractions differs (by blocks of 16 rows).  Returns 0 or 1 + the first
+// column whose radicand was <= 0 or not finite.
 template <int NP>
 __device__ __forceinline__ int chol_blocked(double *G, int S, int n, double s, double *red, double *dd)
 {
+    constexpr int NB = NP / 16;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int li = lane & 15, lk = lane >> 4;
+    for (int idx = t; idx < NP * NP; idx += kCholThreads) {
+        const int r = idx / NP, c = idx % NP;
+        if (c >= n && r <= c) G[r * S + c] = (r == c) ? 1.0 : 0.0;
+    }
     for (int i = t; i < n; i += kCholThreads) G[i * S + i] += s;
     __syncthreads();
-    const int nb = (n + 15) / 16;
-    for (int J = 0; J < nb; ++J) {
+    for (int J = 0; J < NB; ++J) {
         const int j0 = 16 * J;
-        const int w = n - j0 < 16 ? n - j0 : 16;
         // (1) diagonal block
         if (wv == 0) {
-            const int col = j0 + (li < w ? li : 0);
+            const int col = j0 + li;
             double c[16];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) c[k] = (k < w) ? G[(j0 + k) * S + col] : 0.0;
+            for (int k = 0; k < 16; ++k) c[k] = G[(j0 + k) * S + col];
             int bd = 0;
 #pragma unroll
             for (int jj = 0; jj < 16; ++jj) {
-                if (jj >= w) break;
                 const double d = readlane_d(c[jj], jj);
-                if (!(d > 0.0) || !isfinite(d)) {
-                    bd = j0 + jj + 1;
-                    break;
-                }
+                if (bd == 0 && (!(d > 0.0) || !isfinite(d))) bd = j0 + jj + 1;
                 const double rjj = sqrt(d);
                 const double r = (li == jj) ? rjj : c[jj] / rjj;
 #pragma unroll
                 for (int k = jj + 1; k < 16; ++k) c[k] = __builtin_fma(-readlane_d(r, k), r, c[k]);
                 c[jj] = r;
             }
-            if (bd == 0 && lane < w) {
+            if (bd == 0 && lane < 16) {
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
                     if (k <= lane) G[(j0 + k) * S + j0 + lane] = c[k];
@@ -424,33 +425,26 @@ __device__ __forceinline__ int chol_blocked(double *G, int S, int n, double s, d
         const int bd = (int)red[13];
         if (bd) return bd;
         // (2) block row: r_{j, col} = (a_{j, col} - sum_{i < j} r_{i j} r_{i, col}) / r_jj
-        for (int col = j0 + 16 + t; col < n; col += kCholThreads) {
+        for (int col = j0 + 16 + t; col < NP; col += kCholThreads) {
             double a[16];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) a[k] = (k < w) ? G[(j0 + k) * S + col] : 0.0;
+            for (int k = 0; k < 16; ++k) a[k] = G[(j0 + k) * S + col];
 #pragma unroll
             for (int jj = 0; jj < 16; ++jj) {
-                if (jj >= w) break;
                 double v = a[jj];
 #pragma unroll
                 for (int i = 0; i < jj; ++i) v = __builtin_fma(-G[(j0 + i) * S + j0 + jj], a[i], v);
                 a[jj] = v * dd[jj];
             }
 #pragma unroll
-            for (int k = 0; k < 16; ++k)
-                if (k < w) G[(j0 + k) * S + col] = a[k];
+            for (int k = 0; k < 16; ++k) G[(j0 + k) * S + col] = a[k];
         }
         __syncthreads();
-        // (3) trailing upper tiles (K, L), J < K <= L < nb, tile index enumerated row by row
-        const int nr = nb - J - 1;
+        // (3) trailing upper tiles (K, L), J < K <= L < NB, tile index enumerated row by row
+        const int nr = NB - J - 1;
         const int ntile = nr * (nr + 1) / 2;
         for (int tt = wv; tt < ntile; tt += kCholThreads / 64) {
-            int K = 0, rem = tt;
-            while (rem >= nr - K) {
-                rem -= nr - K;
-                ++K;
-            }
-            const int L = K + rem;
+            const int K = tile_row(nr, tt), L = tile_col(nr, tt);
             const int k0 = 16 * (J + 1 + K), l0 = 16 * (J + 1 + L);
             d4 d;
 #pragma unroll
@@ -458,9 +452,7 @@ __device__ __forceinline__ int chol_blocked(double *G, int S, int n, double s, d
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4) {
                 const int row = j0 + 4 * s4 + lk;
-                const double av = row < n ? -G[row * S + k0 + li] : 0.0;
-                const double bv = row < n ? G[row * S + l0 + li] : 0.0;
-                d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
+                d = __builtin_amdgcn_mfma_f64_16x16x4f64(-G[row * S + k0 + li], G[row * S + l0 + li], d, 0, 0, 0);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) G[(k0 + lk + 4 * r) * S + l0 + li] = d[r];
