@@ -242,7 +242,7 @@ KERNEL_PATTERNS = [
     ("trsm_gram", r"k_pass_wide<\d+, 1, (true|false)>"),
     ("trsm", r"k_pass_wide<\d+, 2, (true|false)>"),
     ("chol", r"k_chol<\d+>"),
-    ("reduce", r"k_reduce\("),
+    ("reduce", r"k_reduce_l[12]\("),
     ("finalize_r", r"k_finalize_r<\d+>"),
 ]
 

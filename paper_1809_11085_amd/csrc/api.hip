@@ -78,7 +78,7 @@ scqr_status check_opts(const scqr_opts *o)
 struct Layout {
     int np, nwg, nlvl2;
     int64_t elems;
-    size_t off_ctl, off_G, off_Ge, off_Rt, off_dinv, off_R0, off_R1, off_part, off_lvl2, off_gsum, off_cnt, off_bmax,
+    size_t off_ctl, off_G, off_Ge, off_Rt, off_dinv, off_R0, off_R1, off_part, off_lvl2, off_gsum, off_bmax,
         off_split, total;
 };
 
@@ -111,8 +111,6 @@ Layout layout(int64_t m, int64_t n, bool oblique)
     o += align256(sizeof(double) * (size_t)L.nlvl2 * (size_t)L.elems);
     L.off_gsum = o;
     o += align256(sizeof(double) * (size_t)L.elems);
-    L.off_cnt = o;
-    o += align256(sizeof(uint32_t) * (size_t)((L.elems + 255) / 256));
     L.off_bmax = o;
     o += align256(sizeof(double) * (size_t)L.nwg);
     L.off_split = o;
@@ -135,7 +133,6 @@ Work carve(void *ws, const Layout &L)
     w.partials = reinterpret_cast<double *>(c + L.off_part);
     w.lvl2 = reinterpret_cast<double *>(c + L.off_lvl2);
     w.gsum = reinterpret_cast<double *>(c + L.off_gsum);
-    w.counters = reinterpret_cast<uint32_t *>(c + L.off_cnt);
     w.bmax = reinterpret_cast<double *>(c + L.off_bmax);
     w.Rsplit = L.np == 256 ? reinterpret_cast<double *>(c + L.off_split) : nullptr;
     w.nwg = L.nwg;

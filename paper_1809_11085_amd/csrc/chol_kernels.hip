@@ -26,12 +26,6 @@ __device__ double block_sum(double v, double *scratch)
     return s;
 }
 
-__device__ int block_or(int v, double *scratch)
-{
-    const double s = block_sum(v ? 1.0 : 0.0, scratch);
-    return s > 0.0;
-}
-
 // Assemble an np x np symmetric Gram (stride S) from the reduced tiles (gsum, starting at
 // element offset `base`); the upper triangle is taken and mirrored, entries beyond n are 0.
 // Every thread first issues all of its loads (unrolled) so that they overlap.
@@ -40,7 +34,7 @@ __device__ void assemble(const Work &w, int n, int64_t base, bool f32_layout, do
 {
     constexpr int NT = NP / 16;
     constexpr int T = NT * (NT + 1) / 2;
-    constexpr int CH = T < 16 ? T : 16;
+    constexpr int CH = T <= 36 ? T : 16;  // all loads in flight at once up to NP = 128
     for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) G[(idx / NP) * S + idx % NP] = 0.0;
     __syncthreads();
     for (int u0 = 0; u0 < T; u0 += CH) {
@@ -108,6 +102,30 @@ __device__ __forceinline__ double wave_sum_dpp(double v)
     v += dpp_d<0x141>(v);  // row_half_mirror
     v += dpp_d<0x140>(v);  // row_mirror
     return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// Three fixed-order block sums at once: DPP wave sums, then the waves' sums in wave order
+// (one pair of barriers for the three).
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *scratch)
+{
+    a = wave_sum_dpp(a);
+    b = wave_sum_dpp(b);
+    c = wave_sum_dpp(c);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        scratch[3 * wv] = a;
+        scratch[3 * wv + 1] = b;
+        scratch[3 * wv + 2] = c;
+    }
+    __syncthreads();
+    a = b = c = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+        a += scratch[3 * i];
+        b += scratch[3 * i + 1];
+        c += scratch[3 * i + 2];
+    }
+    __syncthreads();
 }
 
 // Power iteration of the first wave for NP <= 64 with row i of G held in lane i's registers
@@ -542,9 +560,10 @@ __device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const
         dev += d * d;
         if (i == j) tr += a;
     }
-    bad = block_or(bad, red);
-    dev = sqrt(block_sum(dev, red));
-    tr = block_sum(tr, red);
+    double badd = bad ? 1.0 : 0.0;
+    block_sum3(badd, dev, tr, red);
+    bad = badd > 0.0;
+    dev = sqrt(dev);
     if (bad) {
         if (threadIdx.x == 0) {
             ctl->active = 0;
@@ -713,9 +732,8 @@ k_chol_b(const BatchInst *__restrict__ insts, SchedParams sp, int pass, int vari
 }
 
 // Initialise the control block and the caller's info record.
-__device__ __forceinline__ void init_body(Ctl *ctl, scqr_info *info, uint32_t *counters, int ncounters)
+__device__ __forceinline__ void init_body(Ctl *ctl, scqr_info *info)
 {
-    for (int i = threadIdx.x; i < ncounters; i += blockDim.x) counters[i] = 0u;
     if (threadIdx.x == 0) {
         ctl->active = 1;
         ctl->pass = 0;
@@ -736,15 +754,15 @@ __device__ __forceinline__ void init_body(Ctl *ctl, scqr_info *info, uint32_t *c
     }
 }
 
-__global__ void k_init(Ctl *ctl, scqr_info *info, uint32_t *counters, int ncounters)
+__global__ void k_init(Ctl *ctl, scqr_info *info)
 {
-    init_body(ctl, info, counters, ncounters);
+    init_body(ctl, info);
 }
 
 __global__ void k_init_b(const BatchInst *__restrict__ insts)
 {
     const BatchInst I = load_cview(insts + blockIdx.x);
-    init_body(I.w.ctl, I.info, nullptr, 0);
+    init_body(I.w.ctl, I.info);
 }
 
 // G (caller layout, both triangles) from the level-2 partials, for scqr_gram.
@@ -1091,8 +1109,7 @@ hipError_t launch_chol(hipStream_t s, const Problem &p, const Work &w, const Sch
 hipError_t launch_init(hipStream_t s, const Problem &, const Work &w, const SchedParams &sp)
 {
     prof_before(s, "init");
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, w.ctl, sp.info, w.counters,
-                       (int)((w.parts_elems + 255) / 256));
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, w.ctl, sp.info);
     prof_after(s);
     return hipGetLastError();
 }

@@ -643,7 +643,7 @@ k_pass_wide_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__
 }
 
 // ------------------------------------------------------------------------------------------
-// Gram for n <= 128 with 64-row panels shared by 4 waves (wave w owns the upper tiles
+// Gram for n <= 128 with 64-row panels (32 with B) shared by 4 waves (wave w owns the upper tiles
 // t = w, w+4, ...; its operands are read from LDS at wave-uniform tile offsets).  The next
 // panel's loads are issued before the current panel's MFMAs.
 //   OBL: B-Gram X^T (B X), B tridiagonal: the panel carries one halo row above and below and
@@ -664,7 +664,8 @@ k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
     constexpr int WV = NP == 256 ? 8 : 4;  // waves
     constexpr int NTH = 64 * WV;
     static_assert(!(NP == 256 && OBL), "the n = 256 B-Gram uses k_gram_lds");
-    constexpr int PR = NP == 256 ? 32 : 64;  // rows per panel
+    // rows per panel: 32 with B (X and Y = B X both staged, two workgroups per CU) and at n = 256
+    constexpr int PR = (NP == 256 || OBL) ? 32 : 64;
     constexpr int H = OBL ? 1 : 0;
     constexpr int NT = NP / 16;
     constexpr int T = NT * (NT + 1) / 2;
@@ -1358,52 +1359,50 @@ k_gram_lds_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__ 
 }
 
 // ------------------------------------------------------------------------------------------
-// Fixed-order reduction of the per-workgroup partial Grams.  Block (x, g) adds partials
-// p = 32g .. 32g+31 in increasing p for its 256 elements; the last of the blocks of column x
-// to finish (arrival counter after a device-scope fence) adds those level-2 sums in increasing
-// g and writes the reduced tiles.  The result does not depend on which block arrives last.
+// Fixed-order reduction of the per-workgroup partial Grams in two launches: block (x, g) of the
+// first adds partials p = 32g .. 32g+31 in increasing p for its 256 elements; the second adds
+// those level-2 sums in increasing g and writes the reduced tiles.  (Two launches instead of an
+// arrival counter: the kernel boundary orders the level-2 writes before their reads, where a
+// counter would need a device-scope release per block.)
 __global__ void __launch_bounds__(256)
-k_reduce(const double *__restrict__ partials, double *__restrict__ lvl2, double *__restrict__ gsum,
-         uint32_t *__restrict__ counters, int nparts, int nlvl2, int64_t elems,
-         const Ctl *__restrict__ ctl, int pass, int final_gram)
+k_reduce_l1(const double *__restrict__ partials, double *__restrict__ lvl2, int nparts, int64_t elems,
+            const Ctl *__restrict__ ctl, int pass, int final_gram)
 {
-    __shared__ int last;
     if (!gate(ctl, pass)) return;
     if (!gram_needed(ctl, pass, final_gram)) return;
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool live = e < elems;
+    if (e >= elems) return;
     const int g = blockIdx.y;
     const int p0 = 32 * g, p1 = (p0 + 32 < nparts) ? p0 + 32 : nparts;
-    if (live) {
-        double v[32];
+    double v[32];
 #pragma unroll
-        for (int q = 0; q < 32; ++q) v[q] = (p0 + q < p1) ? partials[(int64_t)(p0 + q) * elems + e] : 0.0;
-        double s = 0.0;
+    for (int q = 0; q < 32; ++q) v[q] = (p0 + q < p1) ? partials[(int64_t)(p0 + q) * elems + e] : 0.0;
+    double s = 0.0;
 #pragma unroll
-        for (int q = 0; q < 32; ++q)
-            if (p0 + q < p1) s += v[q];
-        lvl2[(int64_t)g * elems + e] = s;
+    for (int q = 0; q < 32; ++q)
+        if (p0 + q < p1) s += v[q];
+    lvl2[(int64_t)g * elems + e] = s;
+}
+
+__global__ void __launch_bounds__(256)
+k_reduce_l2(const double *__restrict__ lvl2, double *__restrict__ gsum, int nlvl2, int64_t elems,
+            const Ctl *__restrict__ ctl, int pass, int final_gram)
+{
+    if (!gate(ctl, pass)) return;
+    if (!gram_needed(ctl, pass, final_gram)) return;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= elems) return;
+    double s = 0.0;
+    int q = 0;
+    for (; q + 8 <= nlvl2; q += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = lvl2[(int64_t)(q + u) * elems + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
     }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = (atomicAdd(&counters[blockIdx.x], 1u) == (uint32_t)(nlvl2 - 1));
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    if (live) {
-        double s = 0.0;
-        int q = 0;
-        for (; q + 8 <= nlvl2; q += 8) {
-            double v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = lvl2[(int64_t)(q + u) * elems + e];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) s += v[u];
-        }
-        for (; q < nlvl2; ++q) s += lvl2[(int64_t)q * elems + e];
-        gsum[e] = s;
-    }
-    if (threadIdx.x == 0) counters[blockIdx.x] = 0u;
+    for (; q < nlvl2; ++q) s += lvl2[(int64_t)q * elems + e];
+    gsum[e] = s;
 }
 
 // Batched reduction: block (x, i) adds the partials of instance i's tasks t0 .. t1-1 in
@@ -1702,8 +1701,9 @@ hipError_t launch_reduce(hipStream_t s, const Work &w, int pass, int64_t elems, 
 {
     dim3 grid((unsigned)((elems + 255) / 256), (unsigned)w.nlvl2), block(256);
     prof_before(s, "reduce");
-    hipLaunchKernelGGL(k_reduce, grid, block, 0, s, w.partials, w.lvl2, w.gsum, w.counters, w.nwg,
-                       w.nlvl2, elems, w.ctl, pass, final_gram);
+    hipLaunchKernelGGL(k_reduce_l1, grid, block, 0, s, w.partials, w.lvl2, w.nwg, elems, w.ctl, pass, final_gram);
+    hipLaunchKernelGGL(k_reduce_l2, dim3(grid.x), block, 0, s, w.lvl2, w.gsum, w.nlvl2, elems, w.ctl, pass,
+                       final_gram);
     prof_after(s);
     return hipGetLastError();
 }

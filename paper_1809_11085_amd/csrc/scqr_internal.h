@@ -103,7 +103,6 @@ struct Work {
     double *partials;   // nwg x parts_elems
     double *lvl2;       // nlvl2 x parts_elems
     double *gsum;       // parts_elems: the reduced Gram tiles of the last reduction
-    uint32_t *counters; // one arrival counter per 256-element chunk of the reduction
     double *bmax;       // nwg per-workgroup Gershgorin maxima (oblique first pass)
     double *Rsplit;     // np = 256: R~_11, R~_22 (128 x 128 each) and their reciprocal diagonals
     int nwg;            // workgroups (= partial count) of the pass kernels
