@@ -332,61 +332,6 @@ __device__ __forceinline__ double power_lambda(const double *G, int S, int n, do
     }
 }
 
-// In-place upper Cholesky of G + sI (upper triangle of G, stride S), one column per thread
-// (thread l owns column l).  Returns 0 or 1 + the column whose pivot radicand was <= 0 or not
-// finite.  Row j of R is formed from the rows above it (Crout order):
-//   r_jl = ((a_jl - r_0j r_0l) - r_1j r_1l - ...) / r_jj,   l > j,
-// while the pivot radicands d_l = (a_ll + s) - r_0l^2 - r_1l^2 - ... are brought up to date
-// as soon as each r_kl is known (one FMA per column and row), so that r_jj = sqrt(d_j) needs
-// no chain of its own (these radicands are updated in increasing k, as in the textbook
-// algorithm).  The inner dot products only read LDS and are unrolled so that their loads overlap.  With WAVE the
-// first wave alone runs it (n <= 64) and the per-row synchronisation is a wave-level fence.
-template <bool WAVE>
-__device__ int chol_columns(double *G, int S, int n, double s, double *dd)
-{
-    const int l = WAVE ? (threadIdx.x & 63) : threadIdx.x;
-    auto sync = [&]() {
-        if (WAVE)
-            wave_sync_c();
-        else
-            __syncthreads();
-    };
-    if (l < n) dd[l] = G[l * S + l] + s;
-    sync();
-    for (int j = 0; j < n; ++j) {
-        const double d = dd[j];
-        if (!(d > 0.0) || !isfinite(d)) return j + 1;
-        const double rjj = sqrt(d);
-        const bool own = (l > j && l < n);
-        double v = 0.0;
-        if (own) {
-            v = G[j * S + l];
-            const double *cj = G + j;  // cj[k * S] = r_kj
-            const double *cl = G + l;  // cl[k * S] = r_kl
-            int k = 0;
-            for (; k + 8 <= j; k += 8) {
-                double a[8], b[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    a[u] = cj[(k + u) * S];
-                    b[u] = cl[(k + u) * S];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) v = __builtin_fma(-a[u], b[u], v);
-            }
-            for (; k < j; ++k) v = __builtin_fma(-cj[k * S], cl[k * S], v);
-            v = v / rjj;
-        }
-        sync();
-        if (own) {
-            G[j * S + l] = v;
-            dd[l] = __builtin_fma(-v, v, dd[l]);
-        }
-        if (l == j) G[j * S + j] = rjj;
-        sync();
-    }
-    return 0;
-}
 
 // Blocked right-looking upper Cholesky of G + sI for NP >= 128 by the whole workgroup, in
 // 16-column blocks J of the matrix padded to NP with an identity block (rows and columns n..NP-1
@@ -1163,8 +1108,6 @@ hipError_t launch_finalize_r(hipStream_t s, const Problem &p, const Work &w, int
     case 16: hipLaunchKernelGGL((k_finalize_r<16>), dim3(1), dim3(256), 0, s, p, w); break;
     case 32: hipLaunchKernelGGL((k_finalize_r<32>), dim3(1), dim3(256), 0, s, p, w); break;
     case 64: hipLaunchKernelGGL((k_finalize_r<64>), dim3(1), dim3(256), 0, s, p, w); break;
-    case 128: hipLaunchKernelGGL((k_finalize_r<128>), dim3(1), dim3(256), 0, s, p, w); break;
-    case 256: hipLaunchKernelGGL((k_finalize_r<256>), dim3(1), dim3(256), 0, s, p, w); break;
     default: prof_after(s); return hipErrorInvalidValue;
     }
     prof_after(s);

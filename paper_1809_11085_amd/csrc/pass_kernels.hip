@@ -1106,7 +1106,7 @@ k_split256(const double *__restrict__ Rt, const double *__restrict__ dinv, doubl
 }
 
 // ------------------------------------------------------------------------------------------
-// Row-wise substitution for n > 64, one row per thread, 64-column blocks: block J starts from
+// Row-wise substitution of the batched n = 256 class, one row per thread, 64-column blocks: block J starts from
 // x_J, receives -q_k r_kj for every earlier k in increasing order (solved values are re-read
 // from the thread's own output row), then is solved against the diagonal block.
 template <int NP>
@@ -1145,14 +1145,6 @@ trsm_big_body(const Problem &p, const double *__restrict__ Rt, const double *__r
                 if (64 * J + c < n) qr[64 * J + c] = t[c];
         }
     }
-}
-
-template <int NP>
-__global__ void __launch_bounds__(256)
-k_trsm_big(Problem p, const double *__restrict__ Rt, const double *__restrict__ dinv,
-           const Ctl *__restrict__ ctl, int pass)
-{
-    trsm_big_body<NP>(p, Rt, dinv, ctl, pass, (int64_t)blockIdx.x * 256, (int64_t)gridDim.x * 256, p.m);
 }
 
 template <int NP>
@@ -1530,19 +1522,6 @@ static hipError_t launch_gram_lds(hipStream_t s, const Problem &p, const Work &w
     else
         hipLaunchKernelGGL((k_gram_lds<NP, WAVES, false, false, false>), grid, block, 0, s, p,
                            w.partials, w.bmax, w.ctl, pass, final_gram);
-    return hipGetLastError();
-}
-
-template <int NP>
-static hipError_t launch_trsm_big(hipStream_t s, const Problem &p, const Work &w, int pass)
-{
-    const int cus = cu_count();
-    int64_t blocks = (p.m + 255) / 256;
-    const int64_t cap = 4 * (int64_t)cus;
-    if (blocks > cap) blocks = cap;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_trsm_big<NP>), dim3((unsigned)blocks), dim3(256), 0, s, p, factor_of(w, NP, pass),
-                       dinv_of(w, NP, pass), w.ctl, pass);
     return hipGetLastError();
 }
 
