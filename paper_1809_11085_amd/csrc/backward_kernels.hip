@@ -85,7 +85,7 @@ k_bwd_gram(int64_t m, int n, const double *__restrict__ Q, int64_t ldq, const do
     constexpr int NT = NP / 16;
     constexpr int T = NT * (NT + 1) / 2;
     constexpr int TPW = (T + WV - 1) / WV;
-    constexpr int S = NP + 2;
+    constexpr int S = lds_stride_gram(NP);
     constexpr int PP = PR * NP / 2 / NTH;
     static_assert(PP >= 1 && (PR * NP / 2) % NTH == 0, "panel must split over the workgroup");
     __shared__ __attribute__((aligned(16))) double qs[PR * S];

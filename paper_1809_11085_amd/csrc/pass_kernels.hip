@@ -670,7 +670,7 @@ k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
     constexpr int NT = NP / 16;
     constexpr int T = NT * (NT + 1) / 2;
     constexpr int TPW = (T + WV - 1) / WV;
-    constexpr int S = NP + 2;
+    constexpr int S = lds_stride_gram(NP);
     constexpr int PP = PR * NP / 2 / NTH;  // double pairs per thread per panel
     constexpr int64_t E = (int64_t)T * 256;
     __shared__ __attribute__((aligned(16))) double xs[(PR + 2 * H) * S];

@@ -19,6 +19,12 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // Number of 16 x 16 tiles in the upper triangle of an NP x NP matrix (NP = 16 * NT).
 __host__ __device__ constexpr int upper_tiles(int nt) { return nt * (nt + 1) / 2; }
 
+// LDS row stride (in doubles) for panels read as Gram operands (lane l at row l / 16, column
+// l % 16 of a 4 x 16 block): with S = 16 (mod 32) the two rows of each half-wave fall on disjoint
+// halves of the 64 banks, and the bank-conflict counter of the Gram kernels reads 0 on gfx950
+// (against about two conflict cycles per LDS instruction with S = np + 2).
+__host__ __device__ constexpr int lds_stride_gram(int np) { return np % 64 == 16 ? np + 32 : np + 16; }
+
 // Tile t (row-major enumeration of the upper triangle) -> block row I, block column J.
 __host__ __device__ constexpr int tile_row(int nt, int t)
 {
