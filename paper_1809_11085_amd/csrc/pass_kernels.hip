@@ -651,7 +651,7 @@ k_pass_wide_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__
 //        off_k x_{k+1}.
 //   EUC: with OBL, also X^T X (second half of the partial) and the workgroup's Gershgorin
 //        maximum of B (for the first-pass shift of equation (eq:finds2B)).
-//   F32: binary32 MFMA over each panel (64 rows; 32 for n = 256), added to the binary64 tiles
+//   F32: binary32 MFMA over each panel (64 rows; 16 for n = 256), added to the binary64 tiles
 //        after the panel.
 //   BATCH: workgroup b takes task b of the device task table; otherwise workgroup b takes a
 //        contiguous share of the problem's panels.
@@ -664,8 +664,9 @@ k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
     constexpr int WV = NP == 256 ? 8 : 4;  // waves
     constexpr int NTH = 64 * WV;
     static_assert(!(NP == 256 && OBL), "the n = 256 B-Gram uses k_gram_lds");
-    // rows per panel: 32 with B (X and Y = B X both staged, two workgroups per CU) and at n = 256
-    constexpr int PR = (NP == 256 || OBL) ? 32 : 64;
+    // rows per panel: 32 with B (X and Y = B X both staged, two workgroups per CU), 16 at n = 256
+    // (17 tile accumulators per wave leave room for a 16-row prefetch only)
+    constexpr int PR = NP == 256 ? 16 : (OBL ? 32 : 64);
     constexpr int H = OBL ? 1 : 0;
     constexpr int NT = NP / 16;
     constexpr int T = NT * (NT + 1) / 2;
