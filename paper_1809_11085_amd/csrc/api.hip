@@ -155,12 +155,13 @@ scqr_status hip_status(hipError_t e) { return e == hipSuccess ? SCQR_OK : SCQR_E
 
 // ---------------------------------------------------------------- batched planning
 // Instances are grouped by padded width; every class is one launch per step.  A class's rows
-// are cut into tasks of equal size (a multiple of 32 rows, at least kBatchMinRows) so that a
-// launch has about kBatchTargetTasks workgroups; an instance's tasks are contiguous.  The plan
-// depends only on (m_i, n_i) and the options.
+// are cut into tasks of at most rpt rows (a multiple of kBatchRowAlign, at least kBatchMinRows)
+// so that a launch has about kBatchTargetTasks workgroups; each instance is split into
+// ceil(m / rpt) tasks of equal size (up to the alignment), and an instance's tasks are
+// contiguous.  The plan depends only on (m_i, n_i) and the options.
 constexpr int kNumClasses = 5;
 constexpr int kClassNp[kNumClasses] = {16, 32, 64, 128, 256};
-constexpr int64_t kBatchTargetTasks = 1024;
+constexpr int64_t kBatchTargetTasks = 4096;
 constexpr int64_t kBatchMinRows = 1024;
 
 int class_of(int64_t n)
@@ -176,6 +177,7 @@ struct BatchPlan {
     std::vector<int> order;           // instance indices, class-major, ascending within a class
     int cls_first[kNumClasses + 1] = {};
     std::vector<int32_t> ntask;       // per instance
+    std::vector<int64_t> task_rows;   // per instance: rows per task (the last one may be shorter)
     int64_t rows_per_task[kNumClasses] = {};
     int task_first[kNumClasses + 1] = {};
     std::vector<size_t> inst_off;     // per instance: offset of its block in the workspace
@@ -203,6 +205,7 @@ scqr_status plan_batch(int32_t batch, const int64_t *m, const int64_t *n, const 
     bp.P = o.schedule == SCQR_SCHED_FIXED3 ? 3 : o.schedule == SCQR_SCHED_CHOLQR2 ? 2 : o.max_passes;
     bp.slots = bp.P;
     bp.ntask.assign(batch, 0);
+    bp.task_rows.assign(batch, 0);
     bp.inst_off.assign(batch, 0);
     int ntasks = 0;
     for (int c = 0; c < kNumClasses; ++c) {
@@ -220,7 +223,13 @@ scqr_status plan_batch(int32_t batch, const int64_t *m, const int64_t *n, const 
         bp.rows_per_task[c] = rpt;
         for (int k = bp.cls_first[c]; k < (int)bp.order.size(); ++k) {
             const int i = bp.order[k];
-            bp.ntask[i] = (int32_t)((m[i] + rpt - 1) / rpt);
+            // ceil(m / rpt) tasks of equal size (to a multiple of kBatchRowAlign), not full tasks
+            // and a remainder: the longest task of a launch sets its tail
+            const int64_t nt = (m[i] + rpt - 1) / rpt;
+            int64_t rows_i = (m[i] + nt - 1) / nt;
+            rows_i = (rows_i + kBatchRowAlign - 1) / kBatchRowAlign * kBatchRowAlign;
+            bp.ntask[i] = (int32_t)((m[i] + rows_i - 1) / rows_i);
+            bp.task_rows[i] = rows_i;
             ntasks += bp.ntask[i];
         }
     }
@@ -573,8 +582,8 @@ scqr_status scqr_qr_batched(void *stream, int32_t batch, const int64_t *m, const
             for (int q = 0; q < bp.ntask[i]; ++q, ++t) {
                 BatchTask &T = ht[bp.task_first[c] + t];
                 T.inst = k - bp.cls_first[c];
-                T.r0 = (int64_t)q * bp.rows_per_task[c];
-                const int64_t r1 = T.r0 + bp.rows_per_task[c];
+                T.r0 = (int64_t)q * bp.task_rows[i];
+                const int64_t r1 = T.r0 + bp.task_rows[i];
                 T.r1 = r1 < m[i] ? r1 : m[i];
             }
             I.t1 = t;
