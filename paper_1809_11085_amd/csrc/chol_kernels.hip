@@ -336,55 +336,97 @@ __device__ __forceinline__ double power_lambda(const double *G, int S, int n, do
 // Blocked right-looking upper Cholesky of G + sI for NP >= 128 by the whole workgroup, in
 // 16-column blocks J of the matrix padded to NP with an identity block (rows and columns n..NP-1
 // of the upper triangle; the factor of the padded matrix is diag(R, I), so every block is full
-// and every loop has compile-time bounds): (1) the first wave factors the 16 x 16 diagonal block
-// in registers (one column per lane, pivot rows broadcast with readlane), (2) one thread per
-// column solves the block row R_J,K = R_JJ^{-T} A_J,K by forward substitution (multiplying by the
-// reciprocals of the diagonal), (3) the upper tiles of the trailing matrix receive
-// A_KL -= R_J,K^T R_J,L on FP64 MFMA (a 16-row Gram of the block row).  Every entry is reduced
-// by all earlier rows before its own block is factored, as in the textbook algorithm; only the
-// grouping of the subtractions differs (by blocks of 16 rows).  Returns 0 or 1 + the first
-// column whose radicand was <= 0 or not finite.
+// and every loop has compile-time bounds):
+//   (1) the 16 x 16 diagonal block is factored by one wave in registers (one column per lane,
+//       pivot rows broadcast with readlane);
+//   (2) one thread per column solves the block row R_J,K = R_JJ^{-T} A_J,K by forward
+//       substitution (multiplying by the reciprocals of the diagonal);
+//   (3) the upper tiles of the trailing matrix receive A_KL -= R_J,K^T R_J,L on FP64 MFMA.
+// Look-ahead: in (3) the first wave updates the next diagonal tile first and factors it at once
+// (step (1) of block J + 1) while the other waves update the remaining tiles, so the diagonal
+// factorization is off the critical path.  Every entry is reduced by all earlier rows before its
+// own block is factored, as in the textbook algorithm; only the grouping of the subtractions
+// differs (by blocks of 16 rows).  Returns 0 or 1 + the first column whose radicand was <= 0 or
+// not finite.
 template <int NP>
 __device__ __forceinline__ int chol_blocked(double *G, int S, int n, double s, double *red, double *dd)
 {
     constexpr int NB = NP / 16;
+    constexpr int NW = kCholThreads / 64;
+    // NP = 256 keeps G in global memory: the current diagonal block and block row are also kept
+    // in LDS (block row at the Gram-operand stride), so that steps (2) and (3) read their
+    // operands from LDS and only the entries being updated go to global memory
+    constexpr bool GG = NP == 256;
+    constexpr int BS = lds_stride_gram(NP);
+    __shared__ double dbuf[GG ? 256 : 1];
+    __shared__ double brow[GG ? 16 * BS : 1];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int li = lane & 15, lk = lane >> 4;
+    // entry (i, j) of the current diagonal block and (i, c) of the current block row
+    auto rjj_at = [&](int j0, int i, int j) -> double { return GG ? dbuf[i * 16 + j] : G[(j0 + i) * S + j0 + j]; };
+    auto brow_at = [&](int j0, int i, int c) -> double { return GG ? brow[i * BS + c] : G[(j0 + i) * S + c]; };
+    // (1) for block J by the calling wave: R_JJ into G, its reciprocal diagonal into dd, the
+    // breakdown column (or 0) into red[13]
+    // (with GG, from_dbuf: the block was just updated into dbuf by this wave)
+    auto factor_diag = [&](int J, bool from_dbuf) {
+        const int j0 = 16 * J;
+        const int col = j0 + li;
+        double c[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) c[k] = (GG && from_dbuf) ? dbuf[k * 16 + li] : G[(j0 + k) * S + col];
+        int bd = 0;
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const double d = readlane_d(c[jj], jj);
+            if (bd == 0 && (!(d > 0.0) || !isfinite(d))) bd = j0 + jj + 1;
+            const double rjj = sqrt(d);
+            const double r = (li == jj) ? rjj : c[jj] / rjj;
+#pragma unroll
+            for (int k = jj + 1; k < 16; ++k) c[k] = __builtin_fma(-readlane_d(r, k), r, c[k]);
+            c[jj] = r;
+        }
+        if (bd == 0 && lane < 16) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (k <= lane) G[(j0 + k) * S + j0 + lane] = c[k];
+                if (GG) dbuf[k * 16 + lane] = c[k];
+                if (k == lane) dd[lane] = 1.0 / c[k];  // reciprocal of r_{j0 + lane, j0 + lane}
+            }
+        }
+        if (lane == 0) red[13] = (double)bd;
+    };
+    // (3) tile tt of the trailing upper tiles after block J (row-by-row enumeration; tt = 0 is the
+    // next diagonal tile)
+    auto update_tile = [&](int J, int tt) {
+        const int nr = NB - J - 1;
+        const int j0 = 16 * J;
+        const int K = tile_row(nr, tt), L = tile_col(nr, tt);
+        const int k0 = 16 * (J + 1 + K), l0 = 16 * (J + 1 + L);
+        d4 d;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) d[r] = G[(k0 + lk + 4 * r) * S + l0 + li];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int row = 4 * s4 + lk;
+            d = __builtin_amdgcn_mfma_f64_16x16x4f64(-brow_at(j0, row, k0 + li), brow_at(j0, row, l0 + li), d, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            G[(k0 + lk + 4 * r) * S + l0 + li] = d[r];
+            if (GG && tt == 0) dbuf[(lk + 4 * r) * 16 + li] = d[r];
+        }
+    };
+
     for (int idx = t; idx < NP * NP; idx += kCholThreads) {
         const int r = idx / NP, c = idx % NP;
         if (c >= n && r <= c) G[r * S + c] = (r == c) ? 1.0 : 0.0;
     }
     for (int i = t; i < n; i += kCholThreads) G[i * S + i] += s;
     __syncthreads();
+    if (wv == 0) factor_diag(0, false);
+    __syncthreads();
     for (int J = 0; J < NB; ++J) {
         const int j0 = 16 * J;
-        // (1) diagonal block
-        if (wv == 0) {
-            const int col = j0 + li;
-            double c[16];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) c[k] = G[(j0 + k) * S + col];
-            int bd = 0;
-#pragma unroll
-            for (int jj = 0; jj < 16; ++jj) {
-                const double d = readlane_d(c[jj], jj);
-                if (bd == 0 && (!(d > 0.0) || !isfinite(d))) bd = j0 + jj + 1;
-                const double rjj = sqrt(d);
-                const double r = (li == jj) ? rjj : c[jj] / rjj;
-#pragma unroll
-                for (int k = jj + 1; k < 16; ++k) c[k] = __builtin_fma(-readlane_d(r, k), r, c[k]);
-                c[jj] = r;
-            }
-            if (bd == 0 && lane < 16) {
-#pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    if (k <= lane) G[(j0 + k) * S + j0 + lane] = c[k];
-                    if (k == lane) dd[lane] = 1.0 / c[k];  // reciprocal of r_{j0 + lane, j0 + lane}
-                }
-            }
-            if (lane == 0) red[13] = (double)bd;
-        }
-        __syncthreads();
         const int bd = (int)red[13];
         if (bd) return bd;
         // (2) block row: r_{j, col} = (a_{j, col} - sum_{i < j} r_{i j} r_{i, col}) / r_jj
@@ -396,29 +438,27 @@ __device__ __forceinline__ int chol_blocked(double *G, int S, int n, double s, d
             for (int jj = 0; jj < 16; ++jj) {
                 double v = a[jj];
 #pragma unroll
-                for (int i = 0; i < jj; ++i) v = __builtin_fma(-G[(j0 + i) * S + j0 + jj], a[i], v);
+                for (int i = 0; i < jj; ++i) v = __builtin_fma(-rjj_at(j0, i, jj), a[i], v);
                 a[jj] = v * dd[jj];
             }
 #pragma unroll
-            for (int k = 0; k < 16; ++k) G[(j0 + k) * S + col] = a[k];
+            for (int k = 0; k < 16; ++k) {
+                G[(j0 + k) * S + col] = a[k];
+                if (GG) brow[k * BS + col] = a[k];
+            }
         }
+        if (J + 1 == NB) break;
         __syncthreads();
-        // (3) trailing upper tiles (K, L), J < K <= L < NB, tile index enumerated row by row
+        // (3) with look-ahead: the first wave takes the next diagonal tile and factors it, the
+        // other waves the remaining tiles
         const int nr = NB - J - 1;
         const int ntile = nr * (nr + 1) / 2;
-        for (int tt = wv; tt < ntile; tt += kCholThreads / 64) {
-            const int K = tile_row(nr, tt), L = tile_col(nr, tt);
-            const int k0 = 16 * (J + 1 + K), l0 = 16 * (J + 1 + L);
-            d4 d;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) d[r] = G[(k0 + lk + 4 * r) * S + l0 + li];
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {
-                const int row = j0 + 4 * s4 + lk;
-                d = __builtin_amdgcn_mfma_f64_16x16x4f64(-G[row * S + k0 + li], G[row * S + l0 + li], d, 0, 0, 0);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) G[(k0 + lk + 4 * r) * S + l0 + li] = d[r];
+        if (wv == 0) {
+            update_tile(J, 0);
+            wave_sync_c();  // the tile's entries were written by other lanes of this wave
+            factor_diag(J + 1, true);
+        } else {
+            for (int tt = wv; tt < ntile; tt += NW - 1) update_tile(J, tt);
         }
         __syncthreads();
     }
