@@ -28,15 +28,20 @@ __device__ double block_sum(double v, double *scratch)
 
 // Assemble an np x np symmetric Gram (stride S) from the reduced tiles (gsum, starting at
 // element offset `base`); the upper triangle is taken and mirrored, entries beyond n are 0.
-// Every thread first issues all of its loads (unrolled) so that they overlap.
+// Every thread first issues a chunk of its loads (unrolled) so that they overlap.  The thread's
+// share of the checks on the assembled n x n matrix A is accumulated on the way: bad (any entry
+// not finite), dev = ||A - I||_F^2 (off-diagonal entries counted twice) and tr = trace(A).
 template <int NP>
-__device__ void assemble(const Work &w, int n, int64_t base, bool f32_layout, double *G, int S)
+__device__ __forceinline__ void assemble(const Work &w, int n, int64_t base, bool f32_layout, double *G, int S,
+                                         double &bad, double &dev, double &tr)
 {
     constexpr int NT = NP / 16;
     constexpr int T = NT * (NT + 1) / 2;
-    constexpr int CH = T <= 36 ? T : 16;  // all loads in flight at once up to NP = 128
-    for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) G[(idx / NP) * S + idx % NP] = 0.0;
-    __syncthreads();
+    constexpr int CH = T <= 36 ? T : 34;  // all loads in flight at once up to NP = 128, 4 chunks at 256
+    // zero the padding only (rows n.., then columns n.. of rows < n); the rest is written below
+    const int pad = NP - n;
+    for (int idx = threadIdx.x; idx < pad * NP; idx += blockDim.x) G[(n + idx / NP) * S + idx % NP] = 0.0;
+    for (int idx = threadIdx.x; idx < n * pad; idx += blockDim.x) G[(idx / pad) * S + n + idx % pad] = 0.0;
     for (int u0 = 0; u0 < T; u0 += CH) {
         double v[CH];
 #pragma unroll
@@ -54,8 +59,16 @@ __device__ void assemble(const Work &w, int n, int64_t base, bool f32_layout, do
                 acc64_rc(e & 255, ii, jj);
             const int i = 16 * I + ii, j = 16 * J + jj;
             if (i > j || i >= n || j >= n) continue;
-            G[i * S + j] = v[u];
-            G[j * S + i] = v[u];
+            const double a = v[u];
+            G[i * S + j] = a;
+            G[j * S + i] = a;
+            if (!isfinite(a)) bad = 1.0;
+            if (i == j) {
+                dev = __builtin_fma(a - 1.0, a - 1.0, dev);
+                tr += a;
+            } else {
+                dev = __builtin_fma(2.0 * a, a, dev);
+            }
         }
     }
     __syncthreads();
@@ -240,7 +253,7 @@ __device__ __forceinline__ int chol_wave_regs(double *G, int S, int n, double s,
 
 // Power iteration for NP = 128 / 256 by the whole workgroup (same start vector, stopping rule and
 // iteration cap as power_lambda).  NP = 128: threads 2i and 2i + 1 hold the two halves of
-// row i in registers; NP = 256: thread i streams row i from G.  The iterate is broadcast from LDS;
+// row i in registers; NP = 256: thread i streams column i (= row i) from G.  The iterate is broadcast from LDS;
 // the two sums per iteration are reduced in a fixed order (DPP within each wave, then the four
 // wave sums in order), so every thread holds the same values.
 template <int NP>
@@ -273,11 +286,13 @@ __device__ double power_lambda_block(const double *G, int S, int n, double *v, d
                 a3 = __builtin_fma(g[k + 3], vv[k + 3], a3);
             }
         } else {
-            const double *gr = G + (act ? row : 0) * S;
+            // entry (row, k) read as (k, row): G is stored symmetric, and consecutive threads then
+            // read consecutive addresses
+            const double *gc = G + (act ? row : 0);
             for (int k0 = 0; k0 < NP; k0 += 16) {
                 double gb[16];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) gb[u] = (act && k0 + u < n) ? gr[k0 + u] : 0.0;
+                for (int u = 0; u < 16; ++u) gb[u] = (act && k0 + u < n) ? gc[(k0 + u) * S] : 0.0;
 #pragma unroll
                 for (int u = 0; u < 16; u += 4) {
                     a0 = __builtin_fma(gb[u], v[k0 + u], a0);
@@ -531,23 +546,12 @@ __device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const
     double *G = IN_LDS ? lds : w.G;
     const int bit = 1 << (pass - 1);
 
-    assemble<NP>(w, n, 0, f32pass, G, S);
+    double badd = 0.0, dev = 0.0, tr = 0.0;
+    assemble<NP>(w, n, 0, f32pass, G, S, badd, dev, tr);
 
-    // finiteness, ||A - I||_F and trace
-    double dev = 0.0, tr = 0.0;
-    int bad = 0;
-    for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
-        const int i = idx / NP, j = idx % NP;
-        if (i >= n || j >= n) continue;
-        const double a = G[i * S + j];
-        if (!isfinite(a)) bad = 1;
-        const double d = a - (i == j ? 1.0 : 0.0);
-        dev += d * d;
-        if (i == j) tr += a;
-    }
-    double badd = bad ? 1.0 : 0.0;
+    // finiteness, ||A - I||_F and trace (the thread shares came with the assembly)
     block_sum3(badd, dev, tr, red);
-    bad = badd > 0.0;
+    const bool bad = badd > 0.0;
     dev = sqrt(dev);
     if (bad) {
         if (threadIdx.x == 0) {
@@ -572,7 +576,8 @@ __device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const
         const double *Gn = G;
         if (obl_first) {
             // ||X||_2 of (eq:finds2B) is the Euclidean norm: Gram X^T X assembled in w.Ge
-            assemble<NP>(w, n, E, false, w.Ge, S);
+            double b2 = 0.0, d2 = 0.0, t2 = 0.0;
+            assemble<NP>(w, n, E, false, w.Ge, S, b2, d2, t2);
             if (sp.shift_mode == SCQR_SHIFT_FRO) {
                 double t2 = 0.0;
                 for (int i = threadIdx.x; i < n; i += blockDim.x) t2 += w.Ge[i * S + i];
@@ -625,7 +630,8 @@ __device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const
         if (bd == 0 || try_shift || !may_retry) break;
         if (threadIdx.x == 0) info->breakdown_mask |= bit;
         __syncthreads();
-        assemble<NP>(w, n, 0, false, G, S);
+        double b2 = 0.0, d2 = 0.0, t2 = 0.0;
+        assemble<NP>(w, n, 0, false, G, S, b2, d2, t2);
         try_shift = true;
     }
     if (f32pass && bd != 0) {
@@ -654,6 +660,7 @@ __device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const
     // R~ of this pass (identity padding) and its reciprocal diagonal, in the pass's slot
     double *Rslot = w.Rhist + (int64_t)(pass - 1) * NP * NP;
     double *dslot = w.dhist + (int64_t)(pass - 1) * NP;
+#pragma unroll 8
     for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
         const int i = idx / NP, j = idx % NP;
         double v;
