@@ -472,6 +472,36 @@ __device__ __forceinline__ int chol_blocked(double *G, int S, int n, double s, d
             update_tile(J, 0);
             wave_sync_c();  // the tile's entries were written by other lanes of this wave
             factor_diag(J + 1, true);
+        } else if constexpr (GG) {
+            // G in global memory: four tiles per round so that their loads overlap
+            constexpr int NR = 4;
+            for (int t0 = wv; t0 < ntile; t0 += NR * (NW - 1)) {
+                d4 d[NR];
+                int k0[NR], l0[NR];
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    const int tt = t0 + q * (NW - 1) < ntile ? t0 + q * (NW - 1) : t0;
+                    k0[q] = 16 * (J + 1 + tile_row(nr, tt));
+                    l0[q] = 16 * (J + 1 + tile_col(nr, tt));
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) d[q][r] = G[(k0[q] + lk + 4 * r) * S + l0[q] + li];
+                }
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) {
+                        const int row = 4 * s4 + lk;
+                        d[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-brow_at(j0, row, k0[q] + li),
+                                                                    brow_at(j0, row, l0[q] + li), d[q], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    if (t0 + q * (NW - 1) >= ntile) continue;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) G[(k0[q] + lk + 4 * r) * S + l0[q] + li] = d[q][r];
+                }
+            }
         } else {
             for (int tt = wv; tt < ntile; tt += NW - 1) update_tile(J, tt);
         }
