@@ -642,10 +642,19 @@ k_pass_wide_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__
                                   (t.r1 + 63) / 64);
 }
 
+// Threads of the Gram kernel: 8 waves at n = 256 and for the first-pass B-Gram at n >= 64 (its
+// two sets of tile accumulators, X^T B X and X^T X, then fit two waves per SIMD), 4 waves
+// otherwise (measured faster for the B-Gram alone: two 4-wave workgroups per CU).
+constexpr int gram_wide_threads(int np, bool obl, bool euc)
+{
+    return (np == 256 || (obl && euc && np >= 64)) ? 512 : 256;
+}
+
 // ------------------------------------------------------------------------------------------
-// Gram for n <= 128 with 64-row panels (32 with B) shared by 4 waves (wave w owns the upper tiles
-// t = w, w+4, ...; its operands are read from LDS at wave-uniform tile offsets).  The next
-// panel's loads are issued before the current panel's MFMAs.
+// Gram for n <= 256 with panels of 64 rows (32 with B, 16 at n = 256) shared by the waves of the
+// workgroup (gram_wide_threads): wave w owns the upper tiles t = w, w + WV, ...; its operands are
+// read from LDS at wave-uniform tile offsets.  The next panel's loads are issued before the
+// current panel's MFMAs.
 //   OBL: B-Gram X^T (B X), B tridiagonal: the panel carries one halo row above and below and
 //        Y = B X is formed once per panel in LDS, (B x)_k = off_{k-1} x_{k-1} + diag_k x_k +
 //        off_k x_{k+1}.
@@ -656,13 +665,13 @@ k_pass_wide_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__
 //   BATCH: workgroup b takes task b of the device task table; otherwise workgroup b takes a
 //        contiguous share of the problem's panels.
 template <int NP, bool OBL, bool EUC, bool F32, bool BATCH>
-__global__ void __launch_bounds__(NP == 256 ? 512 : 256)
+__global__ void __launch_bounds__(gram_wide_threads(NP, OBL, EUC))
 k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
             const Ctl *__restrict__ ctl, int pass, int final_gram,
             const BatchInst *__restrict__ insts, const BatchTask *__restrict__ tasks)
 {
-    constexpr int WV = NP == 256 ? 8 : 4;  // waves
-    constexpr int NTH = 64 * WV;
+    constexpr int NTH = gram_wide_threads(NP, OBL, EUC);
+    constexpr int WV = NTH / 64;  // waves
     static_assert(!(NP == 256 && OBL), "the n = 256 B-Gram uses k_gram_lds");
     // rows per panel: 32 with B (X and Y = B X both staged, two workgroups per CU), 16 at n = 256
     // (17 tile accumulators per wave leave room for a 16-row prefetch only)
@@ -673,6 +682,7 @@ k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
     constexpr int TPW = (T + WV - 1) / WV;
     constexpr int S = lds_stride_gram(NP);
     constexpr int PP = PR * NP / 2 / NTH;  // double pairs per thread per panel
+    static_assert(PP >= 1 && (PR * NP / 2) % NTH == 0, "panel must split over the workgroup");
     constexpr int64_t E = (int64_t)T * 256;
     __shared__ __attribute__((aligned(16))) double xs[(PR + 2 * H) * S];
     __shared__ __attribute__((aligned(16))) double ys[OBL ? PR * S : 1];
@@ -786,8 +796,8 @@ k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
         if (OBL) {
             // Y = B X for the 64 panel rows
 #pragma unroll
-            for (int i = 0; i < PR * NP / 256; ++i) {
-                const int e = t + 256 * i;
+            for (int i = 0; i < PR * NP / NTH; ++i) {
+                const int e = t + NTH * i;
                 const int r = e / NP, c = e % NP;
                 const double *xc = xs + (r + 1) * S + c;
                 const double bx = cs[3 * r] * xc[-S] + cs[3 * r + 1] * xc[0];
@@ -1548,7 +1558,7 @@ template <int NP>
 static hipError_t launch_gram_wide(hipStream_t s, const Problem &p, const Work &w, int pass, bool f32,
                                    bool obl, bool euc, int final_gram)
 {
-    dim3 grid(w.nwg), block(NP == 256 ? 512 : 256);
+    dim3 grid(w.nwg), block(gram_wide_threads(NP, obl, euc));
     const BatchInst *ni = nullptr;
     const BatchTask *nt = nullptr;
     if constexpr (NP == 256) {
