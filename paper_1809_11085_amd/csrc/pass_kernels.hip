@@ -382,7 +382,10 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
 // an LDS table; diag_solve_steps).  The solved panel is written to Q, and wave w accumulates
 // the upper Gram tiles t = w, w+4, ... over all 64 rows.  The next panel's loads are issued before the current one is solved.
 //   MODE 1: substitution + Gram.  MODE 2: substitution only.  MODE 3: the transposed solve
-//   x R~^T = y (back substitution in blocked order, for the QR adjoint).
+//   x R~^T = y (back substitution in blocked order, for the QR adjoint).  MODE 4: substitution,
+//   then X'_2 = X_2 - Q_1 R~_12 for the panel's rows (WideProd): wave w forms output columns
+//   32 w .. 32 w + 31 from the solved panel in LDS and its slice of -R~_12 held in registers, with
+//   the panel's X_2 loaded before the substitution.
 //   The workgroup takes the 64-row panels [p0, p1).
 // Lane K of every 16-lane row of the wave, broadcast to the whole row (DPP row_newbcast; every
 // lane is written, so the old value is never used).
@@ -433,11 +436,24 @@ __device__ __forceinline__ void wide_gram(d4 (&acc)[TPW], const double *src)
     }
 }
 
+// Second operand of MODE 4 (first half of the n = 256 block solve): after the panel's
+// Q_1 = X_1 R~_11^{-1} is solved, X'_2 = X_2 - Q_1 R~_12 is formed for the same rows.
+struct WideProd {
+    const double *X2;  // m x n2, leading dimension ldx2
+    int64_t ldx2;
+    double *O2;        // m x n2 result (may alias X2)
+    int64_t ldo2;
+    const double *R12; // 128 x n2, leading dimension ldr
+    int64_t ldr;
+    int n2;            // 1 .. 128
+};
+
 template <int NP, int MODE, bool VEC>
 __device__ __forceinline__ void
 pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__restrict__ Rt,
                const double *__restrict__ dinv, double *__restrict__ part_out,
-               const Ctl *__restrict__ ctl, int pass, int final_gram, int64_t p0, int64_t p1)
+               const Ctl *__restrict__ ctl, int pass, int final_gram, int64_t p0, int64_t p1,
+               const WideProd &pr = WideProd{})
 {
     constexpr int WAVES = 4;
     constexpr int PR = 64;
@@ -486,6 +502,37 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
 #pragma unroll
     for (int u = 0; u < TPW; ++u) acc[u] = (d4){0.0, 0.0, 0.0, 0.0};
 
+    // MODE 4: -R~_12 slice of this wave in the B-operand layout, bf[cb][s4] = -R~_12[4 s4 + lk][c]
+    // with c = 32 wv + 16 cb + li; the panel's X_2 in the MFMA result layout
+    constexpr bool PROD = MODE == 4;
+    constexpr int PC = PROD ? 2 : 1, PK = PROD ? NP / 4 : 1;
+    double bf[PC][PK];
+    d4 x2[PROD ? PR / 16 : 1][PC];
+    const bool wprod = PROD && 32 * wv < pr.n2;
+    if constexpr (PROD) {
+#pragma unroll
+        for (int cb = 0; cb < PC; ++cb) {
+            const int c = 32 * wv + 16 * cb + li;
+#pragma unroll
+            for (int s4 = 0; s4 < PK; ++s4)
+                bf[cb][s4] = c < pr.n2 ? -as_global(pr.R12)[(int64_t)(4 * s4 + lk) * pr.ldr + c] : 0.0;
+        }
+    }
+    auto load_x2 = [&](int64_t pnl) {
+        if constexpr (PROD) {
+#pragma unroll
+            for (int g = 0; g < PR / 16; ++g)
+#pragma unroll
+                for (int cb = 0; cb < PC; ++cb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t row = pnl * PR + 16 * g + lk + 4 * r;
+                        const int c = 32 * wv + 16 * cb + li;
+                        x2[g][cb][r] = (wprod && row < p.m && c < pr.n2) ? as_global(pr.X2)[row * pr.ldx2 + c] : 0.0;
+                    }
+        }
+    };
+
     double2 pre[PP];
     auto load_panel = [&](int64_t pnl) {
         const int64_t rb = pnl * PR;
@@ -522,6 +569,7 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
             *reinterpret_cast<double2 *>(P + r * S + c) = pre[i];
         }
         __syncthreads();
+        load_x2(pn);
         if (pn + 1 < p1) load_panel(pn + 1);
 
         // ---- substitution of rows 16 wv .. 16 wv + 15, block by block: the block's MFMA update
@@ -585,6 +633,28 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
             }
         }
 
+        // ---- MODE 4: X'_2 = X_2 - Q_1 R~_12 for the panel (Q_1 in LDS, all waves' strips solved)
+        if (wprod) {
+            const double *abase = P + li * S + lk;
+#pragma unroll
+            for (int g = 0; g < PR / 16; ++g) {
+#pragma unroll
+                for (int cb = 0; cb < PC; ++cb) {
+                    d4 d = x2[g][cb];
+                    const double *arow = abase + 16 * g * S;
+#pragma unroll
+                    for (int s4 = 0; s4 < PK; ++s4)
+                        d = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[4 * s4], bf[cb][s4], d, 0, 0, 0);
+                    const int c = 32 * wv + 16 * cb + li;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t row = r0 + 16 * g + lk + 4 * r;
+                        if (row < p.m && c < pr.n2) as_global(pr.O2)[row * pr.ldo2 + c] = d[r];
+                    }
+                }
+            }
+        }
+
         // ---- Gram tiles of this wave over the 64 rows
         if (want_gram) {
             const double *src = P + lk * S + li;
@@ -622,6 +692,20 @@ k_pass_wide(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
     pass_wide_body<NP, MODE, VEC>(p, Qout, Rt, dinv, partials + (int64_t)blockIdx.x * E, ctl, pass, final_gram,
                                   p0 < p1 ? p0 : p1, p1);
 }
+
+// MODE 4 (NP = 128): the first half of the n = 256 block solve with the product for the second.
+template <bool VEC>
+__global__ void __launch_bounds__(256)
+k_pass_wide4(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
+             const double *__restrict__ dinv, WideProd pr, const Ctl *__restrict__ ctl, int pass)
+{
+    const int64_t npanels = (p.m + 63) / 64;
+    const int64_t per = (npanels + gridDim.x - 1) / gridDim.x;
+    const int64_t p0 = (int64_t)blockIdx.x * per;
+    const int64_t p1 = (p0 + per < npanels) ? p0 + per : npanels;
+    pass_wide_body<128, 4, VEC>(p, Qout, Rt, dinv, nullptr, ctl, pass, 0, p0 < p1 ? p0 : p1, p1, pr);
+}
+
 
 template <int NP, int MODE, bool VEC>
 __global__ void __launch_bounds__(256)
@@ -1601,14 +1685,13 @@ static hipError_t launch_trsm_256(hipStream_t s, const Problem &p, const Work &w
     p1.n = 128;
     p1.np = 128;
     dim3 grid((unsigned)cus), block(256);
-    if (vec)
-        hipLaunchKernelGGL((k_pass_wide<128, 2, true>), grid, block, 0, s, p1, p1.Q, R11, d11, w.partials, w.ctl, pass, 0);
-    else
-        hipLaunchKernelGGL((k_pass_wide<128, 2, false>), grid, block, 0, s, p1, p1.Q, R11, d11, w.partials, w.ctl, pass, 0);
     const int n2 = p.n - 128;
-    hipLaunchKernelGGL((k_mm_breg<128, false, -1>), dim3((unsigned)cus, (unsigned)((n2 + 63) / 64)), block, 0, s, p.m, n2, 128,
-                       (const double *)p.Q, p.ldq, Rt + 128, (int64_t)256, p.X + 128, p.ldx, p.Q + 128, p.ldq,
-                       w.ctl, pass, 0);
+    // Q_1 and X'_2 = X_2 - Q_1 R~_12 in one pass over the rows
+    const WideProd pr{p.X + 128, p.ldx, p.Q + 128, p.ldq, Rt + 128, (int64_t)256, n2};
+    if (vec)
+        hipLaunchKernelGGL((k_pass_wide4<true>), grid, block, 0, s, p1, p1.Q, R11, d11, pr, w.ctl, pass);
+    else
+        hipLaunchKernelGGL((k_pass_wide4<false>), grid, block, 0, s, p1, p1.Q, R11, d11, pr, w.ctl, pass);
     Problem p3 = p;
     p3.n = n2;
     p3.np = 128;
