@@ -1076,17 +1076,19 @@ k_mm(int64_t m, int ncols, int ka, const double *__restrict__ A, int64_t lda, co
 
 // The same product for K = 128 / 256 with the right factor in registers: the workgroup owns a
 // 64-column block, wave w the 16 columns c0 + 16 w .. c0 + 16 w + 15, whose K x 16 slice of B it
-// keeps in registers in the MFMA B-operand layout (loaded once).  32-row panels of A are staged
-// in LDS one panel ahead as in k_mm, and each wave computes both 16-row tiles of its columns:
-// one LDS operand read per MFMA and two independent accumulation chains.  Dispatch order, Base
-// and predication as in k_mm.
+// keeps in registers in the MFMA B-operand layout (loaded once).  Panels of A (32 rows; 16 at
+// K = 256, which keeps the wave within 256 registers, two waves per SIMD) are staged in LDS one
+// panel ahead as in k_mm, and each wave computes the panel's 16-row tiles of its columns: one
+// LDS operand read per MFMA and one accumulation chain per tile.  Dispatch order, Base and
+// predication as in k_mm.
 template <int K, bool TRANS, int SIGN>
 __global__ void __launch_bounds__(256)
 k_mm_breg(int64_t m, int ncols, int ka, const double *__restrict__ A, int64_t lda, const double *__restrict__ Bm,
           int64_t ldb, const double *Base, int64_t ldbase, double *Out, int64_t ldo, const Ctl *__restrict__ ctl,
           int pass, int min_pass)
 {
-    constexpr int PR = 32;
+    constexpr int PR = K == 256 ? 16 : 32;
+    constexpr int RG = PR / 16;
     constexpr int SA = K + 2;
     constexpr int KS = K / 4;
     constexpr int NB = 64;
@@ -1124,7 +1126,7 @@ k_mm_breg(int64_t m, int ncols, int ka, const double *__restrict__ A, int64_t ld
     if (p0 > p1) p0 = p1;
 
     double2 pre[PP];
-    double bpre[2][4];
+    double bpre[RG][4];
     auto load_panel = [&](int64_t pnl) {
 #pragma unroll
         for (int i = 0; i < PP; ++i) {
@@ -1140,7 +1142,7 @@ k_mm_breg(int64_t m, int ncols, int ka, const double *__restrict__ A, int64_t ld
             pre[i] = make_double2(a, b);
         }
 #pragma unroll
-        for (int g = 0; g < 2; ++g)
+        for (int g = 0; g < RG; ++g)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = pnl * PR + 16 * g + (lane >> 4) + 4 * r;
@@ -1157,30 +1159,33 @@ k_mm_breg(int64_t m, int ncols, int ka, const double *__restrict__ A, int64_t ld
             const int e2 = t + 256 * i;
             *reinterpret_cast<double2 *>(as + (e2 / (K / 2)) * SA + 2 * (e2 % (K / 2))) = pre[i];
         }
-        double bcur[2][4];
+        double bcur[RG][4];
 #pragma unroll
-        for (int g = 0; g < 2; ++g)
+        for (int g = 0; g < RG; ++g)
 #pragma unroll
             for (int r = 0; r < 4; ++r) bcur[g][r] = bpre[g][r];
         __syncthreads();
         if (pn + 1 < p1) load_panel(pn + 1);
 
-        d4 acc0 = (d4){0.0, 0.0, 0.0, 0.0}, acc1 = (d4){0.0, 0.0, 0.0, 0.0};
+        d4 acc[RG];
+#pragma unroll
+        for (int g = 0; g < RG; ++g) acc[g] = (d4){0.0, 0.0, 0.0, 0.0};
         const double *a0 = as + (lane & 15) * SA + (lane >> 4);
-        const double *a1 = a0 + 16 * SA;
 #pragma unroll
         for (int s4 = 0; s4 < KS; ++s4) {
-            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[4 * s4], bf[s4], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[4 * s4], bf[s4], acc1, 0, 0, 0);
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+                acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[16 * g * SA + 4 * s4], bf[s4], acc[g], 0, 0, 0);
         }
         // element (i, j) = (lane / 16 + 4 r, lane % 16) of tile g
         if (colok) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row0 = pn * PR + (lane >> 4) + 4 * r, row1 = row0 + 16;
-                if (row0 < m) as_global(Out)[row0 * ldo + col] = SIGN > 0 ? bcur[0][r] + acc0[r] : bcur[0][r] - acc0[r];
-                if (row1 < m) as_global(Out)[row1 * ldo + col] = SIGN > 0 ? bcur[1][r] + acc1[r] : bcur[1][r] - acc1[r];
-            }
+            for (int g = 0; g < RG; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = pn * PR + 16 * g + (lane >> 4) + 4 * r;
+                    if (row < m) as_global(Out)[row * ldo + col] = SIGN > 0 ? bcur[g][r] + acc[g][r] : bcur[g][r] - acc[g][r];
+                }
         }
     }
 }
