@@ -726,12 +726,14 @@ k_pass_wide_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__
                                   (t.r1 + 63) / 64);
 }
 
-// Threads of the Gram kernel: 8 waves at n = 256 and for the first-pass B-Gram at n >= 64 (its
-// two sets of tile accumulators, X^T B X and X^T X, then fit two waves per SIMD), 4 waves
-// otherwise (measured faster for the B-Gram alone: two 4-wave workgroups per CU).
-constexpr int gram_wide_threads(int np, bool obl, bool euc)
+// Threads of the Gram kernel: 16 waves at n = 256 (9 of the 136 tiles per wave, 128 registers:
+// four waves per SIMD; 8 waves for the binary32 variant, whose extra accumulators would spill),
+// 8 waves for the first-pass B-Gram at n >= 64 (its two sets of tile accumulators, X^T B X and
+// X^T X, then fit two waves per SIMD), 4 waves otherwise (measured faster for the B-Gram alone:
+// two 4-wave workgroups per CU).
+constexpr int gram_wide_threads(int np, bool obl, bool euc, bool f32)
 {
-    return (np == 256 || (obl && euc && np >= 64)) ? 512 : 256;
+    return np == 256 ? (f32 ? 512 : 1024) : ((obl && euc && np >= 64) ? 512 : 256);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -749,12 +751,12 @@ constexpr int gram_wide_threads(int np, bool obl, bool euc)
 //   BATCH: workgroup b takes task b of the device task table; otherwise workgroup b takes a
 //        contiguous share of the problem's panels.
 template <int NP, bool OBL, bool EUC, bool F32, bool BATCH>
-__global__ void __launch_bounds__(gram_wide_threads(NP, OBL, EUC))
+__global__ void __launch_bounds__(gram_wide_threads(NP, OBL, EUC, F32))
 k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
             const Ctl *__restrict__ ctl, int pass, int final_gram,
             const BatchInst *__restrict__ insts, const BatchTask *__restrict__ tasks)
 {
-    constexpr int NTH = gram_wide_threads(NP, OBL, EUC);
+    constexpr int NTH = gram_wide_threads(NP, OBL, EUC, F32);
     constexpr int WV = NTH / 64;  // waves
     static_assert(!(NP == 256 && OBL), "the n = 256 B-Gram uses k_gram_lds");
     // rows per panel: 32 with B (X and Y = B X both staged, two workgroups per CU), 16 at n = 256
@@ -1647,7 +1649,7 @@ template <int NP>
 static hipError_t launch_gram_wide(hipStream_t s, const Problem &p, const Work &w, int pass, bool f32,
                                    bool obl, bool euc, int final_gram)
 {
-    dim3 grid(w.nwg), block(gram_wide_threads(NP, obl, euc));
+    dim3 grid(w.nwg), block(gram_wide_threads(NP, obl, euc, f32));
     const BatchInst *ni = nullptr;
     const BatchTask *nt = nullptr;
     if constexpr (NP == 256) {
@@ -1835,10 +1837,12 @@ static void launch_big_b(hipStream_t s, const BatchClass &c, int mode, int pass,
     prof_before(s, f32 ? "b_gram_f32" : "b_gram");
     if constexpr (NP == 128) {
         if (f32)
-            hipLaunchKernelGGL((k_gram_wide<NP, false, false, true, true>), grid, dim3(256), 0, s, Problem{},
+            hipLaunchKernelGGL((k_gram_wide<NP, false, false, true, true>), grid,
+                               dim3(gram_wide_threads(NP, false, false, true)), 0, s, Problem{},
                                c.partials, nullptr, nullptr, pass, final_gram, c.insts, c.tasks);
         else
-            hipLaunchKernelGGL((k_gram_wide<NP, false, false, false, true>), grid, dim3(256), 0, s, Problem{},
+            hipLaunchKernelGGL((k_gram_wide<NP, false, false, false, true>), grid,
+                               dim3(gram_wide_threads(NP, false, false, false)), 0, s, Problem{},
                                c.partials, nullptr, nullptr, pass, final_gram, c.insts, c.tasks);
     } else if (f32) {
         hipLaunchKernelGGL((k_gram_lds_b<NP, WAVES, true>), grid, dim3(WAVES * 64), 0, s, c.insts, c.tasks,
