@@ -75,13 +75,15 @@ size_t backward_ws_bytes(int64_t m, int n)
 // (C reads G at (max(i, j), min(i, j))); tile t = I (I + 1) / 2 + J, and wave w owns the tiles
 // t = w, w + WAVES, ...
 template <int NP>
-__global__ void __launch_bounds__(NP >= 128 ? 512 : 256)
+__global__ void __launch_bounds__(NP == 256 ? 1024 : (NP >= 128 ? 512 : 256))
 k_bwd_gram(int64_t m, int n, const double *__restrict__ Q, int64_t ldq, const double *__restrict__ dQ,
            int64_t lddq, double *__restrict__ partials)
 {
-    constexpr int WV = NP >= 128 ? 8 : 4;
+    constexpr int WV = NP == 256 ? 16 : (NP >= 128 ? 8 : 4);
     constexpr int NTH = 64 * WV;
-    constexpr int PR = NP == 256 ? 16 : 64;  // 16 rows at n = 256: both prefetched panels fit the registers
+    // 16 rows and 16 waves at n = 256: 9 tile accumulators and both prefetched panels fit 128
+    // registers, four waves per SIMD
+    constexpr int PR = NP == 256 ? 16 : 64;
     constexpr int NT = NP / 16;
     constexpr int T = NT * (NT + 1) / 2;
     constexpr int TPW = (T + WV - 1) / WV;
@@ -233,7 +235,7 @@ static hipError_t bwd_impl(hipStream_t s, int64_t m, int n, const double *Q, int
 {
     BwdWork b = carve(ws, m, NP);
     constexpr int NT = NP / 16;
-    constexpr int NTH = NP >= 128 ? 512 : 256;
+    constexpr int NTH = NP == 256 ? 1024 : (NP >= 128 ? 512 : 256);
     const int64_t E = (int64_t)NT * (NT + 1) / 2 * 256;
     if (dQ) {
         prof_before(s, "bwd_gram");
