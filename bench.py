@@ -441,9 +441,12 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "bytes_per_launch": unit_bytes, "avg_launch_ms": round(avg, 5)}
-    # whole-path roofline: bytes (8 + 16 p) m n at 8 TB/s vs flops at 78.6 TFLOP/s
+    # whole-path roofline: bytes (8 + 16 p) m n at 8 TB/s vs flops at 78.6 TFLOP/s; secondary:
+    # the minimum-traffic variant that recomputes every Q from X (X read by each pass's Gram and
+    # by the final substitution, Q written once: 8 (p + 2) m n bytes, 40 m n at p = 3)
     path_bytes = (8 + 16 * p) * m * n
     t_roof = max(path_bytes / (HBM_PEAK_GBS * 1e9), flops / (FP64_PEAK_TFS * 1e12))
+    min_bytes = 8 * (p + 2) * m * n
     result = {
         "metric": METRIC, "value": round(tflops, 3), "unit": "TFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
@@ -454,7 +457,9 @@ def main():
         "roofline": roofline,
         "path_roofline": {"bytes": path_bytes, "flops": flops, "roofline_ms": round(t_roof * 1e3, 4),
                           "frac": round(t_roof * 1e3 / ms, 4),
-                          "achieved_GBs": round(path_bytes / (ms * 1e-3) / 1e9, 1)},
+                          "achieved_GBs": round(path_bytes / (ms * 1e-3) / 1e9, 1),
+                          "min_traffic_bytes": min_bytes,
+                          "frac_min_traffic": round(min_bytes / (HBM_PEAK_GBS * 1e9) * 1e3 / ms, 4)},
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kstats.items()},
         "status": scqr.status_string(info.status),
