@@ -152,8 +152,11 @@ def test_deterministic(scqr):
     assert torch.equal(Q1, Q2) and torch.equal(R1, R2)
 
 
-def test_in_place(scqr):
-    X = synth.randsvd(30000, 48, 1e10, seed=14)
+@pytest.mark.parametrize("m,n", [(30000, 48), (9000, 100), (5000, 200), (3000, 256)])
+def test_in_place(scqr, m, n):
+    # Q written over X: every kernel reads a row panel before writing it (at n = 256 also the
+    # second column block, which the first half's kernel updates to X_2 - Q_1 R~_12 in place)
+    X = synth.randsvd(m, n, 1e10, seed=14 + n)
     Xd = dev(X)
     Q, R, info = scqr.qr(Xd, inplace=True)
     assert info.status == scqr.OK and Q.data_ptr() == Xd.data_ptr()
