@@ -297,13 +297,16 @@ def summarize_profile(d, workload):
     traffic = fetch * 1024 * fs + write * 1024 * ws
     alg = {"trsm_gram": 16 * m * n, "trsm": 16 * m * n, "gram": 8 * m * n}.get(dom, 16 * m * n)
     base = "python3 -u bench.py --workload %s --steps 5 --warmup 2 --no-cpu-baseline --no-accuracy --no-extras" % workload
+    pdir = os.path.relpath(os.path.abspath(d), ROOT)
+    short = base.replace("--steps 5 --warmup 2", "--steps 2 --warmup 1")
+    rp = "rocprofv3 %s --output-format csv -d " + pdir + "/%s -o run -- %s"
     cmds = {
-        "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/trace -o run -- " + base,
-        "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/fetch -o run -- " + base.replace("--steps 5 --warmup 2", "--steps 2 --warmup 1"),
-        "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/write -o run -- " + base.replace("--steps 5 --warmup 2", "--steps 2 --warmup 1"),
-        "copy_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/cfetch -o run -- python3 -u bench.py --copy-calibration",
-        "copy_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/cwrite -o run -- python3 -u bench.py --copy-calibration",
-        "summary": "python3 bench.py --workload %s --summarize-profile gpurun_out/prof" % workload,
+        "trace": rp % ("--kernel-trace --stats", "trace", base),
+        "fetch": rp % ("--pmc FETCH_SIZE", "fetch", short),
+        "write": rp % ("--pmc WRITE_SIZE", "write", short),
+        "copy_fetch": rp % ("--pmc FETCH_SIZE", "cfetch", "python3 -u bench.py --copy-calibration"),
+        "copy_write": rp % ("--pmc WRITE_SIZE", "cwrite", "python3 -u bench.py --copy-calibration"),
+        "summary": "python3 bench.py --workload %s --summarize-profile %s" % (workload, pdir),
     }
     out = {"kernel": dom, "workload": workload, "source_hash": source_hash(),
            "avg_active_ms_rocprof": float(np.mean(act)), "active_launches": int(act.size),
@@ -358,7 +361,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the method shards over rows with one n x n "
-              "all-reduce per pass, but this build runs and reports a single MI355X (--gpus 1).",
+              "all-reduce per pass, but bench.py runs and reports a single MI355X (--gpus 1).",
               file=sys.stderr)
         sys.exit(2)
 

@@ -43,7 +43,7 @@ typedef enum {
     SCQR_OK = 0,
     SCQR_E_INVALID = 1,       /* bad argument (shape, pointer, leading dimension, option)     */
     SCQR_E_WORKSPACE = 2,     /* workspace smaller than scqr_*_workspace_bytes() reported     */
-    SCQR_E_UNSUPPORTED = 3,   /* valid request outside what this build implements             */
+    SCQR_E_UNSUPPORTED = 3,   /* valid request outside what the library implements            */
     SCQR_E_HIP = 4,           /* a HIP runtime call failed                                    */
     SCQR_E_BREAKDOWN = 5,     /* a Cholesky factorization broke down (Algorithm 2 test)       */
     SCQR_E_NOT_CONVERGED = 6, /* adaptive schedule hit max_passes without its stopping test   */

@@ -82,7 +82,7 @@ def test_synchronous_argument_errors(L):
     # R overlapping X
     assert L.scqr_qr(None, 5000, 30, P, 30, None, 0x900000000, 30, P + 8, 30, 0x700000000,
                      1 << 30, None, info) == scqr.E_INVALID
-    # FP32-first with an oblique B is outside this build
+    # FP32-first with an oblique B is not supported
     o2 = scqr._Opts()
     L.scqr_default_opts(ctypes.byref(o2))
     o2.precision = 1
