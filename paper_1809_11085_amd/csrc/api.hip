@@ -316,7 +316,7 @@ const char *scqr_status_string(scqr_status s)
     case SCQR_OK: return "SCQR_OK";
     case SCQR_E_INVALID: return "SCQR_E_INVALID: invalid argument";
     case SCQR_E_WORKSPACE: return "SCQR_E_WORKSPACE: workspace too small or misaligned";
-    case SCQR_E_UNSUPPORTED: return "SCQR_E_UNSUPPORTED: request outside this build";
+    case SCQR_E_UNSUPPORTED: return "SCQR_E_UNSUPPORTED: request outside what the library implements";
     case SCQR_E_HIP: return "SCQR_E_HIP: HIP runtime error";
     case SCQR_E_BREAKDOWN: return "SCQR_E_BREAKDOWN: Cholesky factorization broke down";
     case SCQR_E_NOT_CONVERGED: return "SCQR_E_NOT_CONVERGED: max_passes reached";
