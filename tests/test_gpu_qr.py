@@ -200,3 +200,46 @@ def test_rank_deficient_reports_status(scqr):
     X[:, 5] = X[:, 2]
     _, _, info = scqr.qr(dev(X), schedule="fixed3", debug_zero_shift=True)
     assert info.status == scqr.E_BREAKDOWN
+
+
+@pytest.mark.parametrize("alpha", [11 * (1000 * 50 + 50 * 51) * U, 1e-11, 1e-12, 1e-13, 1e-14, 1e-15])
+def test_shift_study_kappa_of_first_factor(scqr, alpha):
+    # the shift varied at m = 1000, n = 50, kappa = 1e15 (remark after Table 3): the GPU's first
+    # triangular factor, applied by the GPU substitution, gives kappa(Q^(1)) equal to the
+    # exact-arithmetic value sigma_1/sqrt(sigma_1^2+s) / (sigma_n/sqrt(sigma_n^2+s)) and to the
+    # oracle's; where kappa(Q^(1)) is below u^{-1/2}, Algorithm 3 finishes in three passes
+    m, n, kappa = 1000, 50, 1e15
+    X = synth.randsvd(m, n, kappa, seed=61)
+    sv = np.linalg.svd(X, compute_uv=False)
+    Xd = dev(X)
+    Q, R, info = scqr.qr(Xd, schedule="fixed3", shift="custom", custom_alpha=alpha, trace=True)
+    assert not info.breakdown_mask & 1
+    s = info.shift[0]
+    # the power iteration's ||X||_2^2 is a lower bound within 1e-4 on a first-pass spectrum
+    assert s == alpha * info.norm2sq[0] and -1e-12 <= 1 - info.norm2sq[0] / sv[0] ** 2 <= 1e-4
+    Q1 = host(scqr.trsm(Xd, info.trace[0, 1].contiguous()))
+    k = accuracy.cond2(Q1)
+    exact = (sv[0] / np.sqrt(sv[0] ** 2 + s)) / (sv[-1] / np.sqrt(sv[-1] ** 2 + s))
+    assert abs(k / exact - 1) < 0.05
+    ro = oracle.scqr(X, schedule=oracle.FIXED3, shift_mode=oracle.SHIFT_CUSTOM, custom_alpha=alpha,
+                     history=True)
+    ko = accuracy.cond2(oracle.trsm_rows(X, ro.rts[0]))
+    assert abs(k / ko - 1) < 0.05
+    # below u^{-1/2} the two unshifted passes succeed on both sides; above it, whether the
+    # second Cholesky breaks down is decided by rounding and may differ between them
+    if max(k, ko) < 0.5 / np.sqrt(U):
+        assert info.status == scqr.OK and info.passes == 3 == ro.passes
+        assert accuracy.orthogonality(host(Q))[0] <= 1e-13
+
+
+def test_shift_study_small_shift(scqr):
+    # s = u ||X||_2^2: no guarantee against breakdown; without one, kappa(Q^(1)) <= u^{-1/2}
+    X = synth.randsvd(1000, 50, 1e15, seed=61)
+    Xd = dev(X)
+    Q, R, info = scqr.qr(Xd, schedule="fixed3", shift="small", trace=True)
+    assert info.shift[0] == U * info.norm2sq[0]
+    if info.breakdown_mask & 1:
+        assert info.status == scqr.E_BREAKDOWN and info.passes == 0
+    else:
+        Q1 = host(scqr.trsm(Xd, info.trace[0, 1].contiguous()))
+        assert accuracy.cond2(Q1) <= 1 / np.sqrt(U)

@@ -342,3 +342,58 @@ def test_not_converged_cap():
 def test_invalid_shapes():
     r = oracle.scqr(np.zeros((3, 5)))
     assert r.status == oracle.INVALID
+
+
+# ------------------------------------------- shift study of the remark after Table 3 (Figure shift_test)
+SHIFT_STUDY = (1000, 50, 1e15)
+SHIFT_STUDY_ALPHAS = [11 * (1000 * 50 + 50 * 51) * U, 1e-11, 1e-12, 1e-13, 1e-14, 1e-15]
+
+
+def kappa_after_shifted_pass(sv, s):
+    """Exact-arithmetic condition number of X R^{-1} with R^T R = X^T X + s I: the singular
+    values of that factor are sigma_i / sqrt(sigma_i^2 + s), increasing in sigma_i."""
+    return (sv[0] / np.sqrt(sv[0] ** 2 + s)) / (sv[-1] / np.sqrt(sv[-1] ** 2 + s))
+
+
+def test_shift_study_kappa_of_first_factor():
+    # m = 1000, n = 50, kappa = 1e15, the shift varied: kappa(Q^(1)) follows the closed form
+    # above down to s = 1e-15 ||X||^2, stays within (eq:CNreduction), and the paper's shift
+    # (about 6.4e-11 here) leaves it above what (eq:cholqr2gurantee) asks of CholeskyQR2.
+    m, n, kappa = SHIFT_STUDY
+    X = synth.randsvd(m, n, kappa, seed=61)
+    sv = np.linalg.svd(X, compute_uv=False)
+    need = 1.0 / (8 * np.sqrt((m * n + n * (n + 1)) * U))
+    ks = []
+    for a in SHIFT_STUDY_ALPHAS:
+        r = oracle.scqr(X, schedule=oracle.FIXED3, shift_mode=oracle.SHIFT_CUSTOM, custom_alpha=a,
+                        history=True)
+        assert not r.breakdown_mask & 1
+        s = r.shifts[0]
+        assert s == a * r.norm2sq[0] and abs(r.norm2sq[0] / sv[0] ** 2 - 1) < 1e-10
+        k = accuracy.cond2(oracle.trsm_rows(X, r.rts[0]))
+        assert abs(k / kappa_after_shifted_pass(sv, s) - 1) < 0.05
+        assert k <= 2 * np.sqrt(3) * np.sqrt(1 + a * (sv[0] / sv[-1]) ** 2)
+        ks.append(k)
+        # the two unshifted passes of Algorithm 3 go through when kappa(Q^(1)) is below u^{-1/2};
+        # above it nothing is guaranteed (whether the second Cholesky breaks down is rounding)
+        if k < 0.5 / np.sqrt(U):
+            assert r.status == oracle.OK and r.passes == 3
+            assert accuracy.orthogonality(r.Q)[0] < 1e-13
+    assert ks[0] > need
+    assert all(k1 > 2.5 * k2 for k1, k2 in zip(ks, ks[1:]))
+    # the continuation (Algorithm 2) finishes from the paper's shift with extra passes
+    r = oracle.scqr(X, schedule=oracle.ADAPTIVE)
+    assert r.status == oracle.OK and r.passes > 3
+    assert accuracy.orthogonality(r.Q)[0] < 1e-13
+
+
+def test_shift_study_small_shift():
+    # s = u ||X||_2^2: no guarantee against breakdown; without one, kappa(Q^(1)) <= u^{-1/2}
+    m, n, kappa = SHIFT_STUDY
+    X = synth.randsvd(m, n, kappa, seed=61)
+    r = oracle.scqr(X, schedule=oracle.FIXED3, shift_mode=oracle.SHIFT_SMALL, history=True)
+    assert r.shifts[0] == U * r.norm2sq[0]
+    if r.breakdown_mask & 1:
+        assert r.status == oracle.BREAKDOWN and r.passes == 0
+    else:
+        assert accuracy.cond2(oracle.trsm_rows(X, r.rts[0])) <= 1 / np.sqrt(U)
