@@ -8,6 +8,9 @@ shape, adaptive schedule, the paper's shift):
   (the pass count at kappa ~ 1/u is reported: parity unpinned there);
 * m = 10^6, n = 128, kappa = 1e13 with the tridiagonal B: ||Q^T B Q - I||_2 and the residual
   <= 1e-13, and the first shift is equation (eq:finds2B) with the Gershgorin bound of ||B||_2.
+* beyond 2^32 elements (71,303,797 x 64, 17 stacked copies of one (2^22 + 37) x 64 matrix Y,
+  kappa = 1e6): R = sqrt(17) R_Y of the oracle within 1e-10, sampled rows of Q in every copy
+  (the last ones included) equal Q_Y / sqrt(17) of the oracle within 1e-10 and each other to rounding.
 """
 import numpy as np
 import pytest
@@ -94,3 +97,36 @@ def test_full_size_oblique(scqr):
     lam = oracle.lambda_max(oracle.gram(X))
     s_exact = oracle.shift(m, n, lam, bnorm=bn, oblique=True)
     assert s_exact * (1 - 1e-4) <= info.shift[0] <= s_exact * (1 + 1e-6)
+
+
+def test_beyond_2_32_elements(scqr):
+    # X = 17 stacked copies of Y ((2^22 + 37) x 64, kappa = 1e6): 71,303,797 rows and about
+    # 4.56e9 elements, so every copy past the 8th sits beyond 2^31 and the last beyond 2^32
+    # elements.  In exact arithmetic R_X = sqrt(17) R_Y and every block of Q_X is Q_Y / sqrt(17);
+    # the row-wise substitution treats equal rows alike, so the blocks of Q_X agree to rounding.
+    my, n, c = (1 << 22) + 37, 64, 17
+    m = c * my
+    assert m * n > 1 << 32 and m < 1 << 31
+    Y = synth.randsvd(my, n, 1e6, seed=synth.seed_for(1, 3))
+    X = torch.from_numpy(Y).cuda().repeat(c, 1)
+    assert X.shape == (m, n)
+    print(f"factorizing {m} x {n} ({m * n} elements)", flush=True)
+    Q, R, info = scqr.qr(X)
+    assert info.status == scqr.OK
+    del X
+    ro = oracle.scqr(Y, schedule=oracle.ADAPTIVE)
+    assert ro.status == oracle.OK
+    sc = np.sqrt(float(c))
+    Rh = host(R)
+    rerr = np.linalg.norm(Rh - sc * ro.R) / np.linalg.norm(sc * ro.R)
+    base = np.concatenate([[0, 1, my - 1], np.random.default_rng(3).choice(my, 61, replace=False)])
+    rows = np.concatenate([k * my + base for k in range(c)])
+    Qs = host(Q[torch.from_numpy(rows).cuda()]).reshape(c, base.size, n)
+    qerr = np.max(np.abs(Qs[0] - ro.Q[base] / sc))
+    spread = np.max(np.abs(Qs - Qs[0]))
+    print(f"passes {info.passes} (oracle on Y {ro.passes}); ||R - sqrt(17) R_Y|| / ||.|| = {rerr:.2e}; "
+          f"max |Q - Q_Y / sqrt(17)| = {qerr:.2e}; max spread over copies = {spread:.2e}", flush=True)
+    assert rerr <= 1e-10
+    assert qerr <= 1e-10
+    assert spread <= 64 * U * np.max(np.abs(Qs[0]))
+    assert np.abs(Qs[-1, 2]).max() > 0  # the last row of X was written
