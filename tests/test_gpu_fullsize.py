@@ -8,8 +8,8 @@ shape, adaptive schedule, the paper's shift):
   (the pass count at kappa ~ 1/u is reported: parity unpinned there);
 * m = 10^6, n = 128, kappa = 1e13 with the tridiagonal B: ||Q^T B Q - I||_2 and the residual
   <= 1e-13, and the first shift is equation (eq:finds2B) with the Gershgorin bound of ||B||_2.
-* beyond 2^32 elements (71,303,797 x 64, 17 stacked copies of one (2^22 + 37) x 64 matrix Y,
-  kappa = 1e6): R = sqrt(17) R_Y of the oracle within 1e-10, sampled rows of Q in every copy
+* beyond 2^32 elements (n = 64, 128, 256; 17 stacked copies of one (2^(28 - log2 n) + 37) x n matrix
+  Y, kappa = 1e6): R = sqrt(17) R_Y of the oracle within 1e-10, sampled rows of Q in every copy
   (the last ones included) equal Q_Y / sqrt(17) of the oracle within 1e-10 and each other to rounding.
 """
 import numpy as np
@@ -99,15 +99,17 @@ def test_full_size_oblique(scqr):
     assert s_exact * (1 - 1e-4) <= info.shift[0] <= s_exact * (1 + 1e-6)
 
 
-def test_beyond_2_32_elements(scqr):
-    # X = 17 stacked copies of Y ((2^22 + 37) x 64, kappa = 1e6): 71,303,797 rows and about
-    # 4.56e9 elements, so every copy past the 8th sits beyond 2^31 and the last beyond 2^32
-    # elements.  In exact arithmetic R_X = sqrt(17) R_Y and every block of Q_X is Q_Y / sqrt(17);
-    # the row-wise substitution treats equal rows alike, so the blocks of Q_X agree to rounding.
-    my, n, c = (1 << 22) + 37, 64, 17
+@pytest.mark.parametrize("my,n,inst", [((1 << 22) + 37, 64, 3), ((1 << 21) + 37, 128, 4),
+                                       ((1 << 20) + 37, 256, 5)])
+def test_beyond_2_32_elements(scqr, my, n, inst):
+    # X = 17 stacked copies of Y (my x n, kappa = 1e6): about 4.56e9 elements, so the copies past
+    # the 8th sit beyond 2^31 and the last one beyond 2^32 elements.  In exact arithmetic
+    # R_X = sqrt(17) R_Y and every block of Q_X is Q_Y / sqrt(17); the row-wise substitution
+    # treats equal rows alike, so the blocks of Q_X agree to rounding.
+    c = 17
     m = c * my
     assert m * n > 1 << 32 and m < 1 << 31
-    Y = synth.randsvd(my, n, 1e6, seed=synth.seed_for(1, 3))
+    Y = synth.randsvd(my, n, 1e6, seed=synth.seed_for(1, inst))
     X = torch.from_numpy(Y).cuda().repeat(c, 1)
     assert X.shape == (m, n)
     print(f"factorizing {m} x {n} ({m * n} elements)", flush=True)
