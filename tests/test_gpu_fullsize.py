@@ -9,7 +9,8 @@ shape, adaptive schedule, the paper's shift):
 * m = 10^6, n = 128, kappa = 1e13 with the tridiagonal B: ||Q^T B Q - I||_2 and the residual
   <= 1e-13, and the first shift is equation (eq:finds2B) with the Gershgorin bound of ||B||_2.
 * beyond 2^32 elements (n = 64, 128, 256; 17 stacked copies of one (2^(28 - log2 n) + 37) x n matrix
-  Y, kappa = 1e6): R = sqrt(17) R_Y of the oracle within 1e-10, sampled rows of Q in every copy
+  Y, kappa = 1e6; Euclidean and with a block-diagonal tridiagonal B): R = sqrt(17) R_Y of the
+  oracle within 1e-10, sampled rows of Q in every copy
   (the last ones included) equal Q_Y / sqrt(17) of the oracle within 1e-10 and each other to rounding.
 """
 import numpy as np
@@ -99,24 +100,33 @@ def test_full_size_oblique(scqr):
     assert s_exact * (1 - 1e-4) <= info.shift[0] <= s_exact * (1 + 1e-6)
 
 
-@pytest.mark.parametrize("my,n,inst", [((1 << 22) + 37, 64, 3), ((1 << 21) + 37, 128, 4),
-                                       ((1 << 20) + 37, 256, 5)])
-def test_beyond_2_32_elements(scqr, my, n, inst):
+BIG = [((1 << 22) + 37, 64, 3), ((1 << 21) + 37, 128, 4), ((1 << 20) + 37, 256, 5)]
+
+
+def _stacked_case(scqr, my, n, inst, oblique):
     # X = 17 stacked copies of Y (my x n, kappa = 1e6): about 4.56e9 elements, so the copies past
-    # the 8th sit beyond 2^31 and the last one beyond 2^32 elements.  In exact arithmetic
-    # R_X = sqrt(17) R_Y and every block of Q_X is Q_Y / sqrt(17); the row-wise substitution
-    # treats equal rows alike, so the blocks of Q_X agree to rounding.
+    # the 8th sit beyond 2^31 and the last one beyond 2^32 elements.  With B = diag(B_Y, ..., B_Y)
+    # (tridiagonal, a zero off-diagonal entry between copies) X^T B X = 17 Y^T B_Y Y, so in exact
+    # arithmetic R_X = sqrt(17) R_Y and every block of Q_X is Q_Y / sqrt(17); the row-wise
+    # substitution treats equal rows alike, so the blocks of Q_X agree to rounding.
     c = 17
     m = c * my
     assert m * n > 1 << 32 and m < 1 << 31
     Y = synth.randsvd(my, n, 1e6, seed=synth.seed_for(1, inst))
     X = torch.from_numpy(Y).cuda().repeat(c, 1)
     assert X.shape == (m, n)
-    print(f"factorizing {m} x {n} ({m * n} elements)", flush=True)
-    Q, R, info = scqr.qr(X)
+    Bd = By = None
+    if oblique:
+        d, o = synth.tridiag_b(my, seed=synth.seed_for(2, inst))
+        By = (d, o)
+        oX = np.concatenate([np.concatenate([o, [0.0]]) for _ in range(c - 1)] + [o])
+        Bd = (torch.from_numpy(d).cuda().repeat(c), torch.from_numpy(oX).cuda())
+        assert Bd[0].numel() == m and Bd[1].numel() == m - 1
+    print(f"factorizing {m} x {n} ({m * n} elements), oblique {oblique}", flush=True)
+    Q, R, info = scqr.qr(X, B=Bd)
     assert info.status == scqr.OK
     del X
-    ro = oracle.scqr(Y, schedule=oracle.ADAPTIVE)
+    ro = oracle.scqr(Y, tridiag=By, schedule=oracle.ADAPTIVE)
     assert ro.status == oracle.OK
     sc = np.sqrt(float(c))
     Rh = host(R)
@@ -132,3 +142,13 @@ def test_beyond_2_32_elements(scqr, my, n, inst):
     assert qerr <= 1e-10
     assert spread <= 64 * U * np.max(np.abs(Qs[0]))
     assert np.abs(Qs[-1, 2]).max() > 0  # the last row of X was written
+
+
+@pytest.mark.parametrize("my,n,inst", BIG)
+def test_beyond_2_32_elements(scqr, my, n, inst):
+    _stacked_case(scqr, my, n, inst, oblique=False)
+
+
+@pytest.mark.parametrize("my,n,inst", BIG)
+def test_beyond_2_32_elements_oblique(scqr, my, n, inst):
+    _stacked_case(scqr, my, n, inst, oblique=True)
