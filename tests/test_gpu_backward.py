@@ -2,7 +2,8 @@
     M = R dR^T - dQ^T Q,   dX = (dQ + Q copyltu(M)) R^{-T}
 against the oracle's adjoint on the same (Q, R, dQ, dR), through the C ABI, plus the n = 1
 closed form, zero (None) upstream gradients and central finite differences of
-L = <dQ, Q> + <dR, R> through QRFunction (forward and backward on the GPU).
+L = <dQ, Q> + <dR, R> through QRFunction (forward and backward on the GPU), and operands of
+about 4.56e9 elements (beyond 2^32) built from 17 copies of one problem.
 
 The two implementations compute the same formula in binary64 with different summation orders;
 their difference is bounded by a small multiple of u kappa(R) ||dX||.
@@ -117,3 +118,38 @@ def test_backward_full_size(scqr):
     err = np.linalg.norm(dX - ref) / np.linalg.norm(ref)
     print(f"full-size adjoint: ||dX - dX_orc||_F / ||dX_orc||_F = {err:.2e}")
     assert err <= 1e-6
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("my,n,inst", [((1 << 22) + 37, 64, 6), ((1 << 21) + 37, 128, 7),
+                                       ((1 << 20) + 37, 256, 8)])
+def test_backward_beyond_2_32_elements(scqr, my, n, inst):
+    # 17 stacked copies, about 4.56e9 elements per m x n operand: Q = [Q_Y; ...] / sqrt(17),
+    # R = sqrt(17) R_Y, dQ = [dQ_Y; ...], dR = dR_Y give M = sqrt(17) M_Y and every block of dX
+    # equal to dX_Y / sqrt(17); the product with Q and the transposed solve are row-wise, so the
+    # blocks agree to rounding.
+    c = 17
+    m = c * my
+    assert m * n > 1 << 32 and m < 1 << 31
+    sc = np.sqrt(float(c))
+    Y = synth.randsvd(my, n, 1e6, seed=synth.seed_for(5, inst))
+    ry = oracle.scqr(Y, schedule=oracle.ADAPTIVE)
+    assert ry.status == oracle.OK
+    dQy, dRy = synth.upstream_grads(my, n, seed=synth.seed_for(5, 10 + inst))
+    ref = oracle.qr_backward(ry.Q, ry.R, dQy, dRy) / sc
+    del Y
+    Q = dev(ry.Q / sc).repeat(c, 1)
+    dQ = dev(dQy).repeat(c, 1)
+    print(f"adjoint at {m} x {n} ({m * n} elements)", flush=True)
+    dX = scqr.qr_backward(Q, dev(sc * ry.R), dQ, dev(dRy))
+    del Q, dQ
+    base = np.concatenate([[0, 1, my - 1], np.random.default_rng(4).choice(my, 61, replace=False)])
+    rows = np.concatenate([k * my + base for k in range(c)])
+    dXs = host(dX[torch.from_numpy(rows).cuda()]).reshape(c, base.size, n)
+    rel = np.linalg.norm(dXs[0] - ref[base]) / np.linalg.norm(ref[base])
+    spread = np.max(np.abs(dXs - dXs[0]))
+    print(f"||dX - dX_Y / sqrt(17)|| / ||.|| on sampled rows = {rel:.2e}; max spread over copies = "
+          f"{spread:.2e}", flush=True)
+    assert rel <= 64 * n * U * 1e6
+    assert spread <= 64 * U * np.max(np.abs(dXs[0]))
+    assert np.abs(dXs[-1, 2]).max() > 0  # the last row was written
