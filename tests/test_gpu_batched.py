@@ -130,3 +130,41 @@ def test_batched_argument_errors(scqr):
         scqr.qr_batched([X], final_gram=True)
     with pytest.raises(Exception):
         scqr.qr_batched([torch.zeros((4, 8), dtype=torch.float64, device="cuda")])
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("my,n,inst", [((1 << 22) + 37, 64, 11), ((1 << 20) + 37, 256, 12)])
+def test_batched_instance_beyond_2_32_elements(scqr, my, n, inst):
+    # one batched call holding an instance of about 4.56e9 elements (17 stacked copies of Y,
+    # kappa = 1e6) beside two small ones: R = sqrt(17) R_Y and Q = Q_Y / sqrt(17) in every copy
+    # against the oracle's factors of Y, and the small instances against the oracle directly
+    c = 17
+    m = c * my
+    assert m * n > 1 << 32 and m < 1 << 31
+    sc = np.sqrt(float(c))
+    Y = synth.randsvd(my, n, 1e6, seed=synth.seed_for(4, inst))
+    smalls = [synth.randsvd(5000, 16, 1e4, seed=synth.seed_for(4, inst + 100)),
+              synth.randsvd(3001, 128, 1e6, seed=synth.seed_for(4, inst + 200))]
+    Xs = [torch.from_numpy(Y).cuda().repeat(c, 1)] + [torch.from_numpy(S).cuda() for S in smalls]
+    print(f"batched call with a {m} x {n} instance ({m * n} elements)", flush=True)
+    Qs, Rs, infos = scqr.qr_batched(Xs)
+    del Xs
+    assert all(i.status == scqr.OK for i in infos)
+    ro = oracle.scqr(Y, schedule=oracle.ADAPTIVE)
+    Rh = Rs[0].cpu().numpy()
+    rerr = np.linalg.norm(Rh - sc * ro.R) / np.linalg.norm(sc * ro.R)
+    base = np.concatenate([[0, 1, my - 1], np.random.default_rng(5).choice(my, 61, replace=False)])
+    rows = np.concatenate([k * my + base for k in range(c)])
+    Qb = Qs[0][torch.from_numpy(rows).cuda()].cpu().numpy().reshape(c, base.size, n)
+    qerr = np.max(np.abs(Qb[0] - ro.Q[base] / sc))
+    spread = np.max(np.abs(Qb - Qb[0]))
+    print(f"passes {infos[0].passes} (oracle on Y {ro.passes}); ||R - sqrt(17) R_Y|| / ||.|| = {rerr:.2e}; "
+          f"max |Q - Q_Y / sqrt(17)| = {qerr:.2e}; max spread over copies = {spread:.2e}", flush=True)
+    assert rerr <= 1e-10 and qerr <= 1e-10
+    assert spread <= 64 * 2.0 ** -53 * np.max(np.abs(Qb[0]))
+    assert np.abs(Qb[-1, 2]).max() > 0
+    for k, S in enumerate(smalls, start=1):
+        rs = oracle.scqr(S, schedule=oracle.ADAPTIVE)
+        Rk = Rs[k].cpu().numpy()
+        assert np.linalg.norm(Rk - rs.R) <= 1e-10 * np.linalg.norm(rs.R), k
+        assert accuracy.orthogonality(Qs[k].cpu().numpy())[0] <= 1e-13, k
