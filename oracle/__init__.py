@@ -17,7 +17,10 @@ factorization of ill-conditioned matrices"):
 * ``trsm_rows``       Algorithm 1 line 4, row-wise substitution (equation (eq:backward2))
 * ``trmm_upper``      R := R~ R of Algorithms 2 and 3
 * ``shift``           equations (eq:finds2) and (eq:finds2B), remark after Table 3
-* ``scqr``            Algorithms 2, 3, 5 and CholeskyQR2 drivers
+* ``scqr``            Algorithms 2, 3, 5 and CholeskyQR2 drivers.  Where an unshifted Cholesky is
+                      borderline (kappa near 1/u, or an input factor with kappa above u^{-1/2}),
+                      whether it breaks down, and so the pass count, is parity unpinned: rounding
+                      order decides it
 * ``qr_backward``     QR adjoint dX = (dQ + Q copyltu(M)) R^{-T}, M = R dR^T - dQ^T Q
 """
 from __future__ import annotations

@@ -16,7 +16,9 @@
  *
  * Parity status of each function is listed in its comment; every function is pinned by a
  * CPU test except the FP32-first Gram emulation, whose shift rule is not in the paper
- * (parity unpinned beyond its error bound).
+ * (parity unpinned beyond its error bound).  In the drivers, whether a borderline unshifted
+ * Cholesky breaks down (kappa near 1/u, or a factor with kappa above u^{-1/2}) depends on the
+ * rounding order, so the pass count there is parity unpinned.
  */
 #include <math.h>
 #include <stdint.h>
