@@ -106,3 +106,14 @@ def test_product_path_has_no_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(scqr, "_lib", None)
     with pytest.raises(RuntimeError):
         scqr.lib()
+
+
+def test_profile_read_arguments(L):
+    # validation and an empty record need no device
+    import paper_1809_11085_amd as scqr
+    cnt = ctypes.c_int32(-1)
+    assert L.scqr_profile_read(None, 0, None) == scqr.E_INVALID
+    assert L.scqr_profile_read(None, -1, ctypes.byref(cnt)) == scqr.E_INVALID
+    assert L.scqr_profile_read(None, 4, ctypes.byref(cnt)) == scqr.E_INVALID
+    assert L.scqr_profile_enable(0) == scqr.OK
+    assert L.scqr_profile_read(None, 0, ctypes.byref(cnt)) == scqr.OK and cnt.value == 0

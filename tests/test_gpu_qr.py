@@ -243,3 +243,34 @@ def test_shift_study_small_shift(scqr):
     else:
         Q1 = host(scqr.trsm(Xd, info.trace[0, 1].contiguous()))
         assert accuracy.cond2(Q1) <= 1 / np.sqrt(U)
+
+
+def test_profile_records(scqr):
+    # kernel timing: one record per enqueued launch while enabled, none while disabled, cleared
+    # by each read; the timed factorization is bit-identical to an untimed one
+    import ctypes
+
+    Xd = dev(synth.randsvd(20000, 64, 1e12, seed=71))
+    Q0, R0, i0 = scqr.qr(Xd, schedule="adaptive", max_passes=6)
+    scqr.profile_read()
+    scqr.profile_enable(True)
+    try:
+        Q1, R1, i1 = scqr.qr(Xd, schedule="adaptive", max_passes=6)
+        recs = scqr.profile_read()
+        scqr.qr(Xd, schedule="adaptive", max_passes=6)
+        L = scqr.lib()
+        arr = (scqr._KernelStat * 2)()
+        cnt = ctypes.c_int32()
+        assert L.scqr_profile_read(arr, 2, ctypes.byref(cnt)) == scqr.OK
+    finally:
+        scqr.profile_enable(False)
+    assert torch.equal(Q0, Q1) and torch.equal(R0, R1) and i0.passes == i1.passes
+    names = [nm for nm, _ in recs]
+    assert {"init", "gram", "reduce", "chol", "trsm_gram", "finalize_r"} <= set(names)
+    assert names.count("chol") == 6 and names.count("trsm_gram") + names.count("trsm") == 6
+    assert all(ms >= 0.0 for _, ms in recs)
+    # the second factorization's records: the count of all of them, the first two copied
+    assert cnt.value == len(recs) and arr[0].name.decode() == names[0] and arr[0].launches == 1
+    assert scqr.profile_read() == []
+    scqr.qr(Xd)
+    assert scqr.profile_read() == []
