@@ -117,3 +117,45 @@ def test_profile_read_arguments(L):
     assert L.scqr_profile_read(None, 4, ctypes.byref(cnt)) == scqr.E_INVALID
     assert L.scqr_profile_enable(0) == scqr.OK
     assert L.scqr_profile_read(None, 0, ctypes.byref(cnt)) == scqr.OK and cnt.value == 0
+
+
+def test_workspace_sizes_of_batched_and_adjoint(L):
+    # host-side planning only: validation and sizes, no device memory touched
+    import paper_1809_11085_amd as scqr
+    sz = ctypes.c_size_t()
+
+    def arr(v):
+        return (ctypes.c_int64 * len(v))(*v)
+
+    ms, ns = [20000, 5000, 3001, 100000], [64, 16, 128, 256]
+    assert L.scqr_batched_workspace_bytes(4, arr(ms), arr(ns), None, ctypes.byref(sz)) == scqr.OK
+    full = sz.value
+    assert full % 256 == 0 and full > 0
+    assert L.scqr_batched_workspace_bytes(3, arr(ms[:3]), arr(ns[:3]), None, ctypes.byref(sz)) == scqr.OK
+    assert 0 < sz.value < full
+    # FIXED3 keeps three factor slots per instance instead of max_passes
+    o = scqr._Opts()
+    L.scqr_default_opts(ctypes.byref(o))
+    o.schedule = scqr.SCHEDULES["fixed3"]
+    assert L.scqr_batched_workspace_bytes(4, arr(ms), arr(ns), ctypes.byref(o), ctypes.byref(sz)) == scqr.OK
+    assert sz.value < full
+    assert L.scqr_batched_workspace_bytes(0, None, None, None, ctypes.byref(sz)) == scqr.OK
+    assert L.scqr_batched_workspace_bytes(-1, None, None, None, ctypes.byref(sz)) == scqr.E_INVALID
+    assert L.scqr_batched_workspace_bytes(2, None, arr([4, 4]), None, ctypes.byref(sz)) == scqr.E_INVALID
+    assert L.scqr_batched_workspace_bytes(1, arr([10]), arr([20]), None, ctypes.byref(sz)) == scqr.E_INVALID
+    assert L.scqr_batched_workspace_bytes(1, arr([1000]), arr([0]), None, ctypes.byref(sz)) == scqr.E_INVALID
+    assert L.scqr_batched_workspace_bytes(1, arr([1000]), arr([257]), None, ctypes.byref(sz)) == \
+        scqr.E_UNSUPPORTED
+    assert L.scqr_batched_workspace_bytes(1, arr([1000]), arr([8]), None, None) == scqr.E_INVALID
+    o.max_passes = 0
+    o.schedule = scqr.SCHEDULES["adaptive"]
+    assert L.scqr_batched_workspace_bytes(1, arr([1000]), arr([8]), ctypes.byref(o), ctypes.byref(sz)) == \
+        scqr.E_INVALID
+
+    assert L.scqr_backward_workspace_bytes(100000, 64, ctypes.byref(sz)) == scqr.OK and sz.value > 0
+    small = sz.value
+    assert L.scqr_backward_workspace_bytes(100000, 256, ctypes.byref(sz)) == scqr.OK and sz.value > small
+    assert L.scqr_backward_workspace_bytes(10, 20, ctypes.byref(sz)) == scqr.E_INVALID
+    assert L.scqr_backward_workspace_bytes(1000, 0, ctypes.byref(sz)) == scqr.E_INVALID
+    assert L.scqr_backward_workspace_bytes(1000, 257, ctypes.byref(sz)) == scqr.E_INVALID
+    assert L.scqr_backward_workspace_bytes(1000, 8, None) == scqr.E_INVALID
