@@ -274,3 +274,43 @@ def test_profile_records(scqr):
     assert scqr.profile_read() == []
     scqr.qr(Xd)
     assert scqr.profile_read() == []
+
+
+def test_plan_graph_replay(scqr):
+    # a Plan allocates everything up front and its run enqueues kernels only, so it can be
+    # captured in a HIP graph; every replay (eager work and synchronizations in between) equals
+    # the eager factorization bitwise, and a new input copied into the captured X is factored
+    m, n = 50000, 64
+    X = dev(synth.randsvd(m, n, 1e12, seed=81))
+    X2h = synth.randsvd(m, n, 1e6, seed=82)
+    plan = scqr.Plan(m, n, "cuda", schedule="adaptive")
+    plan.run(X)
+    torch.cuda.synchronize()
+    Qe, Re, ie = plan.Q.clone(), plan.R.clone(), plan.read_info()
+    assert ie.status == scqr.OK
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.run(X)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.run(X)
+    for _ in range(4):
+        plan.Q.zero_()
+        plan.R.fill_(7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(plan.Q, Qe) and torch.equal(plan.R, Re)
+        info = plan.read_info()
+        assert info.status == scqr.OK and info.passes == ie.passes and info.shift[0] == ie.shift[0]
+    ref = scqr.Plan(m, n, "cuda", schedule="adaptive")
+    Q2, R2 = ref.run(dev(X2h))
+    torch.cuda.synchronize()
+    X.copy_(dev(X2h))
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(plan.Q, Q2) and torch.equal(plan.R, R2)
+    assert plan.read_info().passes == ref.read_info().passes
