@@ -164,16 +164,70 @@ scqr_status scqr_trsm(void *stream, int64_t m, int64_t n, const double *X, int64
                       size_t ws_bytes);
 
 /*
- * Batched QR of independent problems (X_i m_i x n_i, each row-major with ld = n_i).  Shapes
- * are host arrays; the pointer arrays are host arrays of device pointers.  Every instance
- * runs the schedule in opts and writes its own infos[i] (device array of batch records).
- * Workspace from scqr_batched_workspace_bytes().  Q_i may alias X_i.
+ * Tuning of the batched schedule (not in the paper).  Instances are grouped into classes by
+ * padded width (index c = 0..4 for 16, 32, 64, 128, 256); the rows of a class are cut into tasks,
+ * one workgroup each.  A zero field takes the library default.
+ *   rows_per_task[c]  rows of one task, rounded up to a multiple of 64; default: about 4096
+ *                     tasks per class, at least 1024 rows per task.
+ *   panel_rows[c]     classes of width <= 64 only: rows per wave panel of the fused pass, 32
+ *                     (8 waves per workgroup) or 64 (4 waves); default 32.
+ * The results do not depend on the tuning except through the rounding of the Gram sums (the
+ * row partition changes the summation order).
+ */
+typedef struct {
+    int64_t rows_per_task[5];
+    int32_t panel_rows[5];
+    int32_t reserved[3];
+} scqr_batched_tuning;
+
+/*
+ * Batched QR of independent problems X_i (m_i x n_i, row-major).  m, n and the leading
+ * dimensions ldx, ldq, ldr are host arrays of `batch` entries (ldx, ldq or ldr NULL: ld = n_i;
+ * otherwise ld_i >= n_i); X, Q, R are host arrays of device pointers.  Every instance runs the
+ * schedule in opts and writes its own infos[i] (device array of batch records).  Q_i may alias
+ * X_i exactly (same pointer and leading dimension).  Workspace from
+ * scqr_batched_workspace_bytes() with the same shapes, options and tuning (tune may be NULL).
+ * The call copies the instance and task descriptors to the head of the workspace (an enqueued
+ * host-to-device copy from library-owned pinned memory) and then enqueues the schedule; for
+ * repeated calls on the same buffers, or under graph capture, use the batched plan below.
  */
 scqr_status scqr_batched_workspace_bytes(int32_t batch, const int64_t *m, const int64_t *n,
-                                         const scqr_opts *opts, size_t *bytes);
+                                         const scqr_opts *opts, const scqr_batched_tuning *tune,
+                                         size_t *bytes);
 scqr_status scqr_qr_batched(void *stream, int32_t batch, const int64_t *m, const int64_t *n,
-                            const double *const *X, double *const *Q, double *const *R,
-                            void *ws, size_t ws_bytes, const scqr_opts *opts, scqr_info *infos);
+                            const double *const *X, const int64_t *ldx, double *const *Q,
+                            const int64_t *ldq, double *const *R, const int64_t *ldr, void *ws,
+                            size_t ws_bytes, const scqr_opts *opts,
+                            const scqr_batched_tuning *tune, scqr_info *infos);
+
+/*
+ * Batched plan: the batched factorization of one fixed set of buffers, for repeated calls and
+ * for capture in a HIP graph.
+ *   scqr_batched_plan_create  validates and plans on the host (arguments as scqr_qr_batched,
+ *                             buffers included) and keeps the descriptor image in pinned host
+ *                             memory that the plan allocates; no device work.
+ *   scqr_batched_plan_upload  enqueues the copy of the descriptors to the head of ws on stream
+ *                             (once, and again only if the workspace was overwritten).
+ *   scqr_batched_plan_run     enqueues the schedule on stream: kernel launches only (no copy,
+ *                             memset, allocation or host wait), so it may be captured in a graph
+ *                             and replayed; each run re-initialises every instance's state.
+ *   scqr_batched_plan_tuning  the tuning in effect (rows per task and panel rows per class) and
+ *                             the number of tasks per class (ntasks may be NULL).
+ *   scqr_batched_plan_destroy waits for the plan's upload, frees its host memory (not ws).
+ * Runs of one plan, or of plans sharing a workspace, must not overlap in time.
+ */
+typedef struct scqr_batched_plan_s *scqr_batched_plan;
+scqr_status scqr_batched_plan_create(int32_t batch, const int64_t *m, const int64_t *n,
+                                     const double *const *X, const int64_t *ldx, double *const *Q,
+                                     const int64_t *ldq, double *const *R, const int64_t *ldr,
+                                     void *ws, size_t ws_bytes, const scqr_opts *opts,
+                                     const scqr_batched_tuning *tune, scqr_info *infos,
+                                     scqr_batched_plan *plan);
+scqr_status scqr_batched_plan_upload(scqr_batched_plan plan, void *stream);
+scqr_status scqr_batched_plan_run(scqr_batched_plan plan, void *stream);
+scqr_status scqr_batched_plan_tuning(scqr_batched_plan plan, scqr_batched_tuning *tune,
+                                     int32_t *ntasks);
+scqr_status scqr_batched_plan_destroy(scqr_batched_plan plan);
 
 /*
  * QR adjoint (reverse-mode derivative of X -> (Q, R) for the thin QR with positive diagonal):

@@ -11,8 +11,9 @@ factorization of ill-conditioned matrices"):
 * ``gram``            equation (eq:gram), Algorithm 1 line 1
 * ``gram_tridiag``    X^T B X of Algorithm 4 with tridiagonal B
 * ``gram_dense``      X^T B X with dense B (Table 3)
-* ``gram_f32``        FP32-first Gram emulation (not in the paper; parity unpinned beyond its
-                      error bound)
+* ``gram_f32``        FP32-first Gram emulation (not in the paper; pinned by its error bound,
+                      exact small-integer cases and the closed-form condition number of the
+                      first factor; the rest is parity unpinned)
 * ``chol_upper``      Algorithm 1 line 3, R^T R = A + sI, breakdown report
 * ``trsm_rows``       Algorithm 1 line 4, row-wise substitution (equation (eq:backward2))
 * ``trmm_upper``      R := R~ R of Algorithms 2 and 3
@@ -206,6 +207,14 @@ def shift_f32(n, chain, norm2sq) -> float:
     return lib().orc_shift_f32(int(n), int(chain), float(norm2sq))
 
 
+def f32_chain_rows(n: int) -> int:
+    """Rows accumulated in one binary32 chain of the FP32-first Gram, as the option defines it
+    per padded width (n padded to 16, 32, 64, 128 or 256): 32 up to n = 64, 64 up to n = 128,
+    16 beyond.  The chain length k enters the binary32 shift s32 = 11((k+2) n u32 + n(n+1) u)."""
+    n = int(n)
+    return 32 if n <= 64 else (64 if n <= 128 else 16)
+
+
 @dataclass
 class Result:
     Q: np.ndarray
@@ -223,11 +232,13 @@ class Result:
 
 
 def scqr(X, schedule=FIXED3, shift_mode=SHIFT_PAPER, max_passes=6, B=None, tridiag=None,
-         precision=0, f32_chain=64, force_breakdown_pass=0, zero_shift=False, custom_alpha=0.0,
+         precision=0, f32_chain=None, force_breakdown_pass=0, zero_shift=False, custom_alpha=0.0,
          bnorm=0.0, history=False) -> Result:
     """Run the oracle's driver; ``tridiag=(diag, off)`` or dense ``B`` select the oblique form."""
     X = _c(X)
     m, n = X.shape
+    if f32_chain is None:
+        f32_chain = f32_chain_rows(n)
     o = _Opts(schedule, shift_mode, max_passes, precision, f32_chain, force_breakdown_pass,
               int(bool(zero_shift)), 0, custom_alpha, bnorm)
     info = _Info()

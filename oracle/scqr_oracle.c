@@ -454,11 +454,18 @@ int orc_scqr(int64_t m, int64_t n, const double *X, int64_t ldx, int32_t bkind,
     int passes = 0;
     for (int p = 1; p <= max_p; ++p) {
         const int first = (p == 1);
-        const int f32 = first && opt->precision == 1 && !oblique;
+        int f32 = first && opt->precision == 1 && !oblique;
         /* Gram of the current iterate (Algorithm 2 line 3; Algorithm 3 lines 2, 6, 7). */
-        if (f32)
+        if (f32) {
             orc_gram_f32(m, n, Q, n, opt->f32_chain, A);
-        else if (bkind == ORC_B_TRIDIAG)
+            if (!all_finite(nn, A)) {
+                /* the binary32 Gram overflowed (or X holds a NaN / Inf): the first pass is
+                 * redone in binary64, whose own finiteness test decides the status */
+                info->fell_back = 1;
+                f32 = 0;
+                orc_gram(m, n, Q, n, A);
+            }
+        } else if (bkind == ORC_B_TRIDIAG)
             orc_gram_tridiag(m, n, Q, n, b0, b1, A);
         else if (bkind == ORC_B_DENSE)
             orc_gram_dense(m, n, Q, n, b0, A);

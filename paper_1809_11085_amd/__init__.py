@@ -33,9 +33,31 @@ MAX_PASSES = 16
 
 
 class ScqrError(RuntimeError):
-    def __init__(self, status: int, msg: str):
+    """A failed call: ``status`` is the scqr_status code; for a numerical failure reported on
+    the device (breakdown, non-convergence, non-finite Gram) ``info`` holds the decoded record
+    and ``result`` the outputs as the library left them."""
+
+    def __init__(self, status: int, msg: str, info=None, result=None):
         super().__init__(msg)
         self.status = status
+        self.info = info
+        self.result = result
+
+
+CHECK_MODES = (True, False, "raise", "status")
+
+
+def check_mode(check) -> str:
+    """Normalise the ``check`` argument of ``qr`` / ``qr_batched``: "raise" (True, the default:
+    synchronize, decode, raise ScqrError on a numerical failure), "status" (synchronize and
+    decode, never raise) or "none" (False: return the raw device record, no synchronisation)."""
+    if check is True or check == "raise":
+        return "raise"
+    if check is False or check is None:
+        return "none"
+    if check == "status":
+        return "status"
+    raise ValueError(f"check must be one of {CHECK_MODES}, got {check!r}")
 
 
 class _Opts(ctypes.Structure):
@@ -94,10 +116,21 @@ def lib():
         L.scqr_gram.restype = st
         L.scqr_trsm.argtypes = [P, I64, I64, P, I64, P, I64, P, I64, P, SZ]
         L.scqr_trsm.restype = st
-        L.scqr_batched_workspace_bytes.argtypes = [I32, P, P, ctypes.POINTER(_Opts), ctypes.POINTER(SZ)]
+        L.scqr_batched_workspace_bytes.argtypes = [I32, P, P, ctypes.POINTER(_Opts), P, ctypes.POINTER(SZ)]
         L.scqr_batched_workspace_bytes.restype = st
-        L.scqr_qr_batched.argtypes = [P, I32, P, P, P, P, P, P, SZ, ctypes.POINTER(_Opts), P]
+        L.scqr_qr_batched.argtypes = [P, I32, P, P, P, P, P, P, P, P, P, SZ, ctypes.POINTER(_Opts), P, P]
         L.scqr_qr_batched.restype = st
+        L.scqr_batched_plan_create.argtypes = [I32, P, P, P, P, P, P, P, P, P, SZ, ctypes.POINTER(_Opts), P, P,
+                                               ctypes.POINTER(P)]
+        L.scqr_batched_plan_create.restype = st
+        L.scqr_batched_plan_upload.argtypes = [P, P]
+        L.scqr_batched_plan_upload.restype = st
+        L.scqr_batched_plan_run.argtypes = [P, P]
+        L.scqr_batched_plan_run.restype = st
+        L.scqr_batched_plan_tuning.argtypes = [P, P, P]
+        L.scqr_batched_plan_tuning.restype = st
+        L.scqr_batched_plan_destroy.argtypes = [P]
+        L.scqr_batched_plan_destroy.restype = st
         L.scqr_backward_workspace_bytes.argtypes = [I64, I64, ctypes.POINTER(SZ)]
         L.scqr_backward_workspace_bytes.restype = st
         L.scqr_qr_backward.argtypes = [P, I64, I64, P, I64, P, I64, P, I64, P, I64, P, I64, P, SZ]
@@ -235,11 +268,16 @@ class Plan:
 
 
 def qr(X: torch.Tensor, B=None, *, inplace=False, check=True, trace=False, **opts):
-    """Thin QR X = Q R by shifted Cholesky QR.  Returns (Q, R, info); ``info`` is decoded
-    (after a stream synchronisation) when ``check`` is true, and raised on a numerical
-    failure; otherwise it is the raw device record.  ``B = (diag, off)`` selects the oblique
-    inner product with a tridiagonal SPD B.  ``trace=True`` also returns per-pass input Grams
-    and triangular factors in ``info.trace`` (shape [passes, 2, n, n])."""
+    """Thin QR X = Q R by shifted Cholesky QR.  Returns (Q, R, info).
+
+    ``check`` (see ``check_mode``): True or "raise" (default) synchronizes the stream, decodes
+    ``info`` and raises ScqrError when the factorization failed numerically (breakdown,
+    max_passes reached, non-finite Gram); "status" decodes without raising, so that the caller
+    inspects ``info.status``; False returns the raw device record without synchronizing.
+    ``B = (diag, off)`` selects the oblique inner product with a tridiagonal SPD B.
+    ``trace=True`` also returns per-pass input Grams and triangular factors in ``info.trace``
+    (shape [passes, 2, n, n])."""
+    mode = check_mode(check)
     m, n = X.shape
     tr = None
     if trace:
@@ -248,14 +286,14 @@ def qr(X: torch.Tensor, B=None, *, inplace=False, check=True, trace=False, **opt
     plan = Plan(m, n, X.device, B=B, inplace=inplace, trace_ptr=tr.data_ptr() if tr is not None else None,
                 **opts)
     Q, R = plan.run(X)
-    if not check:
+    if mode == "none":
         return Q, R, plan.info
     torch.cuda.current_stream(X.device).synchronize()
     info = plan.read_info()
     if tr is not None:
         info.trace = tr[:max(info.passes, 1)]
-    if info.status not in (OK,) and check == "raise":
-        _check(info.status, "scqr_qr")
+    if info.status != OK and mode == "raise":
+        raise ScqrError(info.status, f"scqr_qr: {status_string(info.status)}", info, (Q, R))
     return Q, R, info
 
 
@@ -290,81 +328,186 @@ def trsm(X: torch.Tensor, R: torch.Tensor, out: torch.Tensor = None) -> torch.Te
     return Q
 
 
-def qr_batched(Xs, *, inplace=False, check=True, **opts):
-    """Factor a list of independent X_i (each m_i x n_i, contiguous).  Returns (Qs, Rs, infos)."""
+NUM_CLASSES = 5
+CLASS_WIDTHS = (16, 32, 64, 128, 256)
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("rows_per_task", ctypes.c_int64 * NUM_CLASSES), ("panel_rows", ctypes.c_int32 * NUM_CLASSES),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+def class_of(n: int) -> int:
+    """Width class of an instance: index of the padded width 16, 32, 64, 128 or 256."""
+    for c, w in enumerate(CLASS_WIDTHS):
+        if n <= w:
+            return c
+    raise ValueError(f"n = {n} exceeds {CLASS_WIDTHS[-1]}")
+
+
+def _tuning(t):
+    """A scqr_batched_tuning from None, a _Tuning, or a dict {"rows_per_task": [5 ints],
+    "panel_rows": [5 ints]} (zeros take the library defaults)."""
+    if t is None or isinstance(t, _Tuning):
+        return t
+    tt = _Tuning()
+    for c, v in enumerate(t.get("rows_per_task", [0] * NUM_CLASSES)):
+        tt.rows_per_task[c] = int(v)
+    for c, v in enumerate(t.get("panel_rows", [0] * NUM_CLASSES)):
+        tt.panel_rows[c] = int(v)
+    return tt
+
+
+def tuning_dict(t: _Tuning) -> dict:
+    return {"rows_per_task": [int(v) for v in t.rows_per_task], "panel_rows": [int(v) for v in t.panel_rows]}
+
+
+def _batch_arrays(mats):
+    b = len(mats)
+    ptrs, lds = [], []
+    for M in mats:
+        p, ld = _mat(M, "batched matrix")
+        ptrs.append(p)
+        lds.append(ld)
+    return (ctypes.c_void_p * b)(*ptrs), (ctypes.c_int64 * b)(*lds)
+
+
+def _decode_batch(infos, b, mode, what, result):
+    dec = [decode_info(infos[i]) for i in range(b)]
+    bad = [i for i, inf in enumerate(dec) if inf.status != OK]
+    if bad and mode == "raise":
+        raise ScqrError(dec[bad[0]].status, f"{what}: instance {bad[0]} (and {len(bad) - 1} more): "
+                        f"{status_string(dec[bad[0]].status)}", dec, result)
+    return dec
+
+
+def qr_batched(Xs, *, inplace=False, check=True, tuning=None, **opts):
+    """Factor a list of independent X_i (each m_i x n_i, row-major; a leading dimension larger
+    than n_i is allowed).  Returns (Qs, Rs, infos).  ``check`` as in ``qr``: "raise" (default)
+    raises ScqrError, with every decoded record in ``.info``, when any instance failed
+    numerically; "status" returns the decoded records; False the raw device records.
+    ``tuning``: None (library defaults) or a dict as taken by ``_tuning``."""
+    mode = check_mode(check)
     if len(Xs) == 0:
         return [], [], []
     dev = Xs[0].device
     b = len(Xs)
-    for X in Xs:
-        _mat(X, "X")
-        if not X.is_contiguous():
-            raise ValueError("batched X_i must be contiguous")
+    xp, ldx = _batch_arrays(Xs)
     ms = (ctypes.c_int64 * b)(*[int(X.shape[0]) for X in Xs])
     ns = (ctypes.c_int64 * b)(*[int(X.shape[1]) for X in Xs])
     o = _opts(**opts)
+    tu = _tuning(tuning)
     sz = ctypes.c_size_t()
-    _check(lib().scqr_batched_workspace_bytes(b, ms, ns, ctypes.byref(o), ctypes.byref(sz)),
-           "scqr_batched_workspace_bytes")
+    _check(lib().scqr_batched_workspace_bytes(b, ms, ns, ctypes.byref(o), ctypes.byref(tu) if tu else None,
+                                              ctypes.byref(sz)), "scqr_batched_workspace_bytes")
     buf, ws = _workspace(sz.value, dev)
-    Qs = list(Xs) if inplace else [torch.empty_like(X) for X in Xs]
+    Qs = list(Xs) if inplace else [torch.empty((X.shape[0], X.shape[1]), dtype=torch.float64, device=dev) for X in Xs]
     Rs = [torch.empty((X.shape[1], X.shape[1]), dtype=torch.float64, device=dev) for X in Xs]
     infos = torch.zeros((b, INFO_BYTES), dtype=torch.uint8, device=dev)
-    xp = (ctypes.c_void_p * b)(*[X.data_ptr() for X in Xs])
-    qp = (ctypes.c_void_p * b)(*[Q.data_ptr() for Q in Qs])
-    rp = (ctypes.c_void_p * b)(*[R.data_ptr() for R in Rs])
-    _check(lib().scqr_qr_batched(_stream(dev), b, ms, ns, xp, qp, rp, ws, sz.value, ctypes.byref(o),
-                                 infos.data_ptr()), "scqr_qr_batched")
-    if not check:
+    qp, ldq = _batch_arrays(Qs)
+    rp, ldr = _batch_arrays(Rs)
+    _check(lib().scqr_qr_batched(_stream(dev), b, ms, ns, xp, ldx, qp, ldq, rp, ldr, ws, sz.value,
+                                 ctypes.byref(o), ctypes.byref(tu) if tu else None, infos.data_ptr()),
+           "scqr_qr_batched")
+    if mode == "none":
         return Qs, Rs, (infos, buf)
     torch.cuda.current_stream(dev).synchronize()
-    return Qs, Rs, [decode_info(infos[i]) for i in range(b)]
+    return Qs, Rs, _decode_batch(infos, b, mode, "scqr_qr_batched", (Qs, Rs))
 
 
 class BatchedPlan:
-    """Pre-allocated workspace, outputs and pointer tables for repeated batched factorizations
-    of one list of shapes (``run`` allocates nothing)."""
+    """The batched factorization of fixed shapes on fixed buffers, for repeated calls and graph
+    capture: workspace, outputs, info records and the library's batched plan (its descriptors
+    uploaded to the workspace once).  ``run()`` enqueues kernel launches only, so it may be
+    captured in a ``torch.cuda.CUDAGraph`` and replayed.
 
-    def __init__(self, shapes, device="cuda", inplace=False, **opts):
+    The inputs are the tensors ``Xs`` given here (new values are copied into them, e.g. with
+    ``X.copy_``), or, when ``Xs`` is None, tensors the plan allocates (``plan.Xs``).  Passing
+    other tensors to ``run`` re-binds the plan on the host first (not under capture).
+    ``tuning``: None (defaults), a dict (see ``_tuning``), or "auto" to pick it with the
+    autotuner (``paper_1809_11085_amd.autotune``: timed trials, cached in a JSON file)."""
+
+    def __init__(self, shapes, device="cuda", inplace=False, Xs=None, tuning=None, **opts):
         self.dev = torch.device(device)
         self.shapes = [(int(m), int(n)) for m, n in shapes]
         self.b = len(self.shapes)
+        if self.b == 0:
+            raise ValueError("empty batch")
         self.inplace = inplace
+        self.opts_kw = dict(opts)
         self.opts = _opts(**opts)
+        if isinstance(tuning, str) and tuning == "auto":
+            from . import autotune
+            tuning = autotune.tune(self.shapes, device=self.dev, **opts)
+        self.tuning = _tuning(tuning)
         self.ms = (ctypes.c_int64 * self.b)(*[m for m, _ in self.shapes])
         self.ns = (ctypes.c_int64 * self.b)(*[n for _, n in self.shapes])
         sz = ctypes.c_size_t()
         _check(lib().scqr_batched_workspace_bytes(self.b, self.ms, self.ns, ctypes.byref(self.opts),
-                                                  ctypes.byref(sz)), "scqr_batched_workspace_bytes")
+                                                  self._tref(), ctypes.byref(sz)), "scqr_batched_workspace_bytes")
         self.ws_bytes = sz.value
         self._ws_buf, self.ws = _workspace(self.ws_bytes, self.dev)
-        self.Qs = None if inplace else [torch.empty((m, n), dtype=torch.float64, device=self.dev)
-                                        for m, n in self.shapes]
+        if Xs is None:
+            Xs = [torch.empty((m, n), dtype=torch.float64, device=self.dev) for m, n in self.shapes]
         self.Rs = [torch.empty((n, n), dtype=torch.float64, device=self.dev) for _, n in self.shapes]
         self.infos = torch.zeros((self.b, INFO_BYTES), dtype=torch.uint8, device=self.dev)
-        self._rp = (ctypes.c_void_p * self.b)(*[R.data_ptr() for R in self.Rs])
-        self._qp = None if inplace else (ctypes.c_void_p * self.b)(*[Q.data_ptr() for Q in self.Qs])
-        self._xkey = None
+        self._plan = None
+        self._bind(Xs)
 
-    def run(self, Xs):
+    def _tref(self):
+        return ctypes.byref(self.tuning) if self.tuning is not None else None
+
+    def _bind(self, Xs):
         if len(Xs) != self.b:
             raise ValueError("batch size does not match the plan")
-        key = tuple(X.data_ptr() for X in Xs)
-        if key != self._xkey:
-            for X, (m, n) in zip(Xs, self.shapes):
-                _mat(X, "X")
-                if tuple(X.shape) != (m, n) or not X.is_contiguous():
-                    raise ValueError("batched X_i must be contiguous and match the plan's shapes")
-            self._xp = (ctypes.c_void_p * self.b)(*key)
-            self._xkey = key
-        qp = self._xp if self.inplace else self._qp
-        _check(lib().scqr_qr_batched(_stream(self.dev), self.b, self.ms, self.ns, self._xp, qp, self._rp,
-                                     self.ws, self.ws_bytes, ctypes.byref(self.opts), self.infos.data_ptr()),
-               "scqr_qr_batched")
-        return (Xs if self.inplace else self.Qs), self.Rs
+        for X, (m, n) in zip(Xs, self.shapes):
+            _mat(X, "X")
+            if tuple(X.shape) != (m, n):
+                raise ValueError("batched X_i must match the plan's shapes")
+        self._destroy()
+        self.Xs = list(Xs)
+        if self.inplace:
+            self.Qs = self.Xs
+        elif getattr(self, "Qs", None) is None:
+            self.Qs = [torch.empty((m, n), dtype=torch.float64, device=self.dev) for m, n in self.shapes]
+        xp, ldx = _batch_arrays(self.Xs)
+        qp, ldq = _batch_arrays(self.Qs)
+        rp, ldr = _batch_arrays(self.Rs)
+        h = ctypes.c_void_p()
+        _check(lib().scqr_batched_plan_create(self.b, self.ms, self.ns, xp, ldx, qp, ldq, rp, ldr, self.ws,
+                                              self.ws_bytes, ctypes.byref(self.opts), self._tref(),
+                                              self.infos.data_ptr(), ctypes.byref(h)), "scqr_batched_plan_create")
+        self._plan = h
+        _check(lib().scqr_batched_plan_upload(self._plan, _stream(self.dev)), "scqr_batched_plan_upload")
+        self._key = tuple(X.data_ptr() for X in self.Xs)
+
+    def run(self, Xs=None):
+        """Enqueue the factorization on the current stream; returns (Qs, Rs)."""
+        if Xs is not None and tuple(X.data_ptr() for X in Xs) != self._key:
+            self._bind(Xs)
+        _check(lib().scqr_batched_plan_run(self._plan, _stream(self.dev)), "scqr_batched_plan_run")
+        return self.Qs, self.Rs
+
+    def tuning_in_effect(self):
+        """(tuning dict, tasks per class) that the library planned."""
+        t = _Tuning()
+        nt = (ctypes.c_int32 * NUM_CLASSES)()
+        _check(lib().scqr_batched_plan_tuning(self._plan, ctypes.byref(t), nt), "scqr_batched_plan_tuning")
+        return tuning_dict(t), [int(v) for v in nt]
 
     def read_infos(self):
         return [decode_info(self.infos[i]) for i in range(self.b)]
+
+    def _destroy(self):
+        if getattr(self, "_plan", None) is not None:
+            lib().scqr_batched_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self._destroy()
+        except Exception:
+            pass
 
 
 def qr_backward(Q: torch.Tensor, R: torch.Tensor, dQ: torch.Tensor = None,

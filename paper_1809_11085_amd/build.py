@@ -28,22 +28,43 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source for gfx950 into libscqr.so (always recompiles)."""
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           *sources(), "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libscqr.so")
     noise = [l for l in (res.stdout + res.stderr).splitlines()
              if l.strip() and "packed-fp32-ops" not in l and "ignoring feature" not in l]
-    if verbose and noise:
+    return res.returncode, noise
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source for gfx950 (one hipcc per source, in parallel) and link
+    libscqr.so (always recompiles)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    srcs = sources()
+    objs = [os.path.join(objdir, os.path.basename(f)[:-4] + ".o") for f in srcs]
+    cflags = [f for f in FLAGS if f != "-shared"]
+    jobs = [[hipcc, *cflags, *inc, "-c", f, "-o", o] for f, o in zip(srcs, objs)]
+    workers = max(1, min(len(jobs), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(workers) as ex:
+        results = list(ex.map(lambda c: _run(c, verbose), jobs))
+    failed = False
+    for (rc, noise), f in zip(results, srcs):
+        if rc != 0 or (verbose and noise):
+            sys.stderr.write("\n".join(noise) + "\n")
+        failed |= rc != 0
+    if failed:
+        raise RuntimeError("hipcc failed building libscqr.so")
+    tmp = LIB + ".tmp"
+    rc, noise = _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp], verbose)
+    if rc != 0:
         sys.stderr.write("\n".join(noise) + "\n")
+        raise RuntimeError("hipcc failed linking libscqr.so")
     os.replace(tmp, LIB)
     return LIB
 

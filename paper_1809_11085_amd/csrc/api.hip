@@ -5,6 +5,7 @@
 #include <atomic>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -155,10 +156,10 @@ scqr_status hip_status(hipError_t e) { return e == hipSuccess ? SCQR_OK : SCQR_E
 
 // ---------------------------------------------------------------- batched planning
 // Instances are grouped by padded width; every class is one launch per step.  A class's rows
-// are cut into tasks of at most rpt rows (a multiple of kBatchRowAlign, at least kBatchMinRows)
-// so that a launch has about kBatchTargetTasks workgroups; each instance is split into
-// ceil(m / rpt) tasks of equal size (up to the alignment), and an instance's tasks are
-// contiguous.  The plan depends only on (m_i, n_i) and the options.
+// are cut into tasks of at most rpt rows (a multiple of kBatchRowAlign; by default at least
+// kBatchMinRows, about kBatchTargetTasks tasks per class, or the caller's tuning); each instance
+// is split into ceil(m / rpt) tasks of equal size (up to the alignment), and an instance's tasks
+// are contiguous.  The plan depends only on (m_i, n_i), the options and the tuning.
 constexpr int kNumClasses = 5;
 constexpr int kClassNp[kNumClasses] = {16, 32, 64, 128, 256};
 constexpr int64_t kBatchTargetTasks = 4096;
@@ -179,6 +180,7 @@ struct BatchPlan {
     std::vector<int32_t> ntask;       // per instance
     std::vector<int64_t> task_rows;   // per instance: rows per task (the last one may be shorter)
     int64_t rows_per_task[kNumClasses] = {};
+    int panel_rows[kNumClasses] = {};
     int task_first[kNumClasses + 1] = {};
     std::vector<size_t> inst_off;     // per instance: offset of its block in the workspace
     size_t off_inst = 0, off_task = 0, off_blocks = 0, off_part[kNumClasses] = {}, total = 0;
@@ -194,9 +196,23 @@ size_t inst_block_bytes(int np, int slots)
     return b;
 }
 
-scqr_status plan_batch(int32_t batch, const int64_t *m, const int64_t *n, const scqr_opts &o, BatchPlan &bp)
+scqr_status check_tuning(const scqr_batched_tuning *t)
+{
+    if (!t) return SCQR_OK;
+    for (int c = 0; c < kNumClasses; ++c) {
+        if (t->rows_per_task[c] < 0 || t->rows_per_task[c] > ((int64_t)1 << 40)) return SCQR_E_INVALID;
+        if (t->panel_rows[c] != 0 && t->panel_rows[c] != 32 && t->panel_rows[c] != 64) return SCQR_E_INVALID;
+        if (t->panel_rows[c] == 64 && kClassNp[c] > 64) return SCQR_E_INVALID;
+    }
+    return SCQR_OK;
+}
+
+scqr_status plan_batch(int32_t batch, const int64_t *m, const int64_t *n, const scqr_opts &o,
+                       const scqr_batched_tuning *tune, BatchPlan &bp)
 {
     scqr_status st = check_opts(&o);
+    if (st != SCQR_OK) return st;
+    st = check_tuning(tune);
     if (st != SCQR_OK) return st;
     for (int32_t i = 0; i < batch; ++i) {
         if (n[i] < 1 || m[i] < n[i]) return SCQR_E_INVALID;
@@ -207,20 +223,26 @@ scqr_status plan_batch(int32_t batch, const int64_t *m, const int64_t *n, const 
     bp.ntask.assign(batch, 0);
     bp.task_rows.assign(batch, 0);
     bp.inst_off.assign(batch, 0);
-    int ntasks = 0;
+    int64_t ntasks = 0;
     for (int c = 0; c < kNumClasses; ++c) {
         bp.cls_first[c] = (int)bp.order.size();
-        bp.task_first[c] = ntasks;
+        bp.task_first[c] = (int)ntasks;
         int64_t rows = 0;
         for (int32_t i = 0; i < batch; ++i)
             if (class_of(n[i]) == c) {
                 bp.order.push_back(i);
                 rows += m[i];
             }
-        int64_t rpt = (rows + kBatchTargetTasks - 1) / kBatchTargetTasks;
+        int64_t rpt;
+        if (tune && tune->rows_per_task[c] > 0) {
+            rpt = tune->rows_per_task[c];
+        } else {
+            rpt = (rows + kBatchTargetTasks - 1) / kBatchTargetTasks;
+            if (rpt < kBatchMinRows) rpt = kBatchMinRows;
+        }
         rpt = (rpt + kBatchRowAlign - 1) / kBatchRowAlign * kBatchRowAlign;
-        if (rpt < kBatchMinRows) rpt = kBatchMinRows;
         bp.rows_per_task[c] = rpt;
+        bp.panel_rows[c] = (tune && tune->panel_rows[c] == 64) ? 64 : 32;
         for (int k = bp.cls_first[c]; k < (int)bp.order.size(); ++k) {
             const int i = bp.order[k];
             // ceil(m / rpt) tasks of equal size (to a multiple of kBatchRowAlign), not full tasks
@@ -232,9 +254,10 @@ scqr_status plan_batch(int32_t batch, const int64_t *m, const int64_t *n, const 
             bp.task_rows[i] = rows_i;
             ntasks += bp.ntask[i];
         }
+        if (ntasks > INT32_MAX / 2) return SCQR_E_UNSUPPORTED;  // one workgroup per task
     }
     bp.cls_first[kNumClasses] = (int)bp.order.size();
-    bp.task_first[kNumClasses] = ntasks;
+    bp.task_first[kNumClasses] = (int)ntasks;
     size_t o2 = 0;
     bp.off_inst = o2;
     o2 += align256(sizeof(BatchInst) * (size_t)batch);
@@ -252,6 +275,168 @@ scqr_status plan_batch(int32_t batch, const int64_t *m, const int64_t *n, const 
     }
     bp.total = o2;
     return SCQR_OK;
+}
+
+// Arguments of one batched factorization (host arrays of the caller).
+struct BatchArgs {
+    int32_t batch;
+    const int64_t *m, *n;
+    const double *const *X;
+    const int64_t *ldx;
+    double *const *Q;
+    const int64_t *ldq;
+    double *const *R;
+    const int64_t *ldr;
+    void *ws;
+    size_t ws_bytes;
+    scqr_info *infos;
+};
+
+int64_t ld_of(const int64_t *ld, int32_t i, const int64_t *n) { return ld ? ld[i] : n[i]; }
+
+// Pointer, leading-dimension, aliasing and workspace checks of a planned batch.
+scqr_status check_batch_args(const BatchArgs &a, const BatchPlan &bp)
+{
+    if (!a.X || !a.Q || !a.R || !a.infos || !a.ws) return SCQR_E_INVALID;
+    if (a.ws_bytes < bp.total || (reinterpret_cast<uintptr_t>(a.ws) & 255)) return SCQR_E_WORKSPACE;
+    for (int32_t i = 0; i < a.batch; ++i) {
+        const int64_t lx = ld_of(a.ldx, i, a.n), lq = ld_of(a.ldq, i, a.n), lr = ld_of(a.ldr, i, a.n);
+        if (lx < a.n[i] || lq < a.n[i] || lr < a.n[i]) return SCQR_E_INVALID;
+        if (!a.X[i] || !a.Q[i] || !a.R[i]) return SCQR_E_INVALID;
+        const size_t xb = mat_bytes(a.m[i], a.n[i], lx), qb = mat_bytes(a.m[i], a.n[i], lq),
+                     rb = mat_bytes(a.n[i], a.n[i], lr);
+        if (a.Q[i] != a.X[i] && ranges_overlap(a.X[i], xb, a.Q[i], qb)) return SCQR_E_INVALID;
+        if (a.Q[i] == a.X[i] && lq != lx) return SCQR_E_INVALID;
+        if (ranges_overlap(a.R[i], rb, a.X[i], xb) || ranges_overlap(a.R[i], rb, a.Q[i], qb)) return SCQR_E_INVALID;
+        if (ranges_overlap(a.ws, bp.total, a.X[i], xb) || ranges_overlap(a.ws, bp.total, a.Q[i], qb) ||
+            ranges_overlap(a.ws, bp.total, a.R[i], rb))
+            return SCQR_E_INVALID;
+    }
+    return SCQR_OK;
+}
+
+// The descriptor image (instances in class order, then tasks) for the head of the workspace,
+// and the per-class launch descriptions that point into the workspace.
+void build_descriptors(const BatchArgs &a, const BatchPlan &bp, std::vector<unsigned char> &host,
+                       BatchClass (&cls)[kNumClasses])
+{
+    char *base = static_cast<char *>(a.ws);
+    host.assign(bp.off_blocks, 0);
+    BatchInst *hi = reinterpret_cast<BatchInst *>(host.data() + bp.off_inst);
+    BatchTask *ht = reinterpret_cast<BatchTask *>(host.data() + bp.off_task);
+    const BatchInst *dinst = reinterpret_cast<const BatchInst *>(base + bp.off_inst);
+    const BatchTask *dtask = reinterpret_cast<const BatchTask *>(base + bp.off_task);
+    for (int c = 0; c < kNumClasses; ++c) {
+        const int np = kClassNp[c];
+        const int64_t elems = pass_partial_elems(np, false);
+        BatchClass &bc = cls[c];
+        bc.np = np;
+        bc.ninst = bp.cls_first[c + 1] - bp.cls_first[c];
+        bc.ntasks = bp.task_first[c + 1] - bp.task_first[c];
+        bc.insts = dinst + bp.cls_first[c];
+        bc.tasks = dtask + bp.task_first[c];
+        bc.partials = reinterpret_cast<double *>(base + bp.off_part[c]);
+        bc.vec = true;
+        bc.pr = bp.panel_rows[c];
+        int t = 0;
+        for (int k = bp.cls_first[c]; k < bp.cls_first[c + 1]; ++k) {
+            const int i = bp.order[k];
+            const int64_t lx = ld_of(a.ldx, i, a.n), lq = ld_of(a.ldq, i, a.n), lr = ld_of(a.ldr, i, a.n);
+            BatchInst &I = hi[k];
+            I.p.m = a.m[i];
+            I.p.n = (int)a.n[i];
+            I.p.np = np;
+            I.p.X = a.X[i];
+            I.p.ldx = lx;
+            I.p.Q = a.Q[i];
+            I.p.ldq = lq;
+            I.p.R = a.R[i];
+            I.p.ldr = lr;
+            I.p.zero = 0;
+            char *blk = base + bp.inst_off[i];
+            size_t o2 = 0;
+            I.w.ctl = reinterpret_cast<Ctl *>(blk + o2);
+            o2 += align256(sizeof(Ctl));
+            I.w.Rhist = reinterpret_cast<double *>(blk + o2);
+            o2 += align256(sizeof(double) * np * np * bp.slots);
+            I.w.dhist = reinterpret_cast<double *>(blk + o2);
+            o2 += align256(sizeof(double) * np * bp.slots);
+            I.w.gsum = reinterpret_cast<double *>(blk + o2);
+            o2 += align256(sizeof(double) * elems);
+            if (np > 128) {
+                I.w.G = reinterpret_cast<double *>(blk + o2);
+                o2 += align256(sizeof(double) * np * (np + 1));
+                I.w.Racc[0] = reinterpret_cast<double *>(blk + o2);
+                o2 += align256(sizeof(double) * np * np);
+                I.w.Racc[1] = reinterpret_cast<double *>(blk + o2);
+            }
+            I.w.parts_elems = elems;
+            I.info = a.infos + i;
+            I.t0 = t;
+            for (int q = 0; q < bp.ntask[i]; ++q, ++t) {
+                BatchTask &T = ht[bp.task_first[c] + t];
+                T.inst = k - bp.cls_first[c];
+                T.r0 = (int64_t)q * bp.task_rows[i];
+                const int64_t r1 = T.r0 + bp.task_rows[i];
+                T.r1 = r1 < a.m[i] ? r1 : a.m[i];
+            }
+            I.t1 = t;
+            if ((a.n[i] & 1) || (lx & 1) || (lq & 1) || (reinterpret_cast<uintptr_t>(a.X[i]) & 15) ||
+                (reinterpret_cast<uintptr_t>(a.Q[i]) & 15))
+                bc.vec = false;
+        }
+    }
+}
+
+SchedParams batch_sched(const scqr_opts &o)
+{
+    SchedParams sp{};
+    sp.schedule = o.schedule;
+    sp.shift_mode = o.shift_mode;
+    sp.precision = o.precision;
+    sp.max_passes = o.max_passes;
+    sp.final_gram = 0;
+    sp.force_bd = o.debug_force_breakdown_pass;
+    sp.zero_shift = o.debug_zero_shift;
+    sp.oblique = 0;
+    sp.custom_alpha = o.custom_alpha;
+    sp.bnorm_user = 0.0;
+    sp.trace = nullptr;
+    sp.info = nullptr;
+    return sp;
+}
+
+// The batched schedule: kernels only (no copy, memset or host wait), so that it can be
+// captured in a graph once the descriptors are in the workspace.
+hipError_t enqueue_batched(hipStream_t s, const BatchPlan &bp, const BatchClass (&cls)[kNumClasses],
+                           const scqr_opts &o)
+{
+    const SchedParams sp = batch_sched(o);
+    const bool f32 = o.precision == SCQR_PREC_FP32_FIRST;
+    hipError_t e = hipSuccess;
+    // one launch per class and step; classes of the same step are independent
+    for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) e = launch_init_b(s, cls[c]);
+    for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
+        e = launch_pass_b(s, cls[c], 0, 0, f32, 0);
+        if (e == hipSuccess) e = launch_reduce_b(s, cls[c], 0, 0);
+        if (e == hipSuccess) e = launch_chol_b(s, cls[c], sp, 1, 0);
+    }
+    if (f32) {
+        for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
+            e = launch_pass_b(s, cls[c], 0, -1, false, 0);
+            if (e == hipSuccess) e = launch_reduce_b(s, cls[c], -1, 0);
+            if (e == hipSuccess) e = launch_chol_b(s, cls[c], sp, 1, 1);
+        }
+    }
+    for (int pass = 1; pass <= bp.P && e == hipSuccess; ++pass) {
+        for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
+            e = launch_pass_b(s, cls[c], 1, pass, false, 0);
+            if (e == hipSuccess) e = launch_reduce_b(s, cls[c], pass, 0);
+            if (e == hipSuccess && pass < bp.P) e = launch_chol_b(s, cls[c], sp, pass + 1, 0);
+        }
+    }
+    for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) e = launch_finalize_b(s, cls[c]);
+    return e;
 }
 
 // Host-to-device upload of the batched descriptors through pinned staging buffers owned by the
@@ -292,6 +477,23 @@ hipError_t upload(hipStream_t s, void *dst, const void *src, size_t bytes)
     return hipEventRecord(st.done, s);
 }
 
+}  // namespace
+
+// A batched plan: the planned schedule and the descriptor image of one set of buffers, kept in
+// the plan's own pinned memory.
+struct scqr_batched_plan_s {
+    scqr_opts o;
+    BatchPlan bp;
+    BatchClass cls[kNumClasses];
+    std::vector<unsigned char> image;   // descriptor image for the head of ws
+    void *ws = nullptr;
+    void *pinned = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool uploaded = false;
+};
+
+namespace {
 }  // namespace
 
 extern "C" {
@@ -484,7 +686,8 @@ scqr_status scqr_trsm(void *stream, int64_t m, int64_t n, const double *X, int64
 }
 
 scqr_status scqr_batched_workspace_bytes(int32_t batch, const int64_t *m, const int64_t *n,
-                                         const scqr_opts *opts, size_t *bytes)
+                                         const scqr_opts *opts, const scqr_batched_tuning *tune,
+                                         size_t *bytes)
 {
     if (!bytes || batch < 0 || (batch > 0 && (!m || !n))) return SCQR_E_INVALID;
     scqr_opts o;
@@ -493,19 +696,21 @@ scqr_status scqr_batched_workspace_bytes(int32_t batch, const int64_t *m, const 
     else
         scqr_default_opts(&o);
     BatchPlan bp;
-    scqr_status st = plan_batch(batch, m, n, o, bp);
+    scqr_status st = plan_batch(batch, m, n, o, tune, bp);
     if (st != SCQR_OK) return st;
     *bytes = bp.total;
     return SCQR_OK;
 }
 
 scqr_status scqr_qr_batched(void *stream, int32_t batch, const int64_t *m, const int64_t *n,
-                            const double *const *X, double *const *Q, double *const *R, void *ws,
-                            size_t ws_bytes, const scqr_opts *opts, scqr_info *infos)
+                            const double *const *X, const int64_t *ldx, double *const *Q,
+                            const int64_t *ldq, double *const *R, const int64_t *ldr, void *ws,
+                            size_t ws_bytes, const scqr_opts *opts,
+                            const scqr_batched_tuning *tune, scqr_info *infos)
 {
     if (batch < 0) return SCQR_E_INVALID;
     if (batch == 0) return SCQR_OK;
-    if (!m || !n || !X || !Q || !R || !infos || !ws) return SCQR_E_INVALID;
+    if (!m || !n) return SCQR_E_INVALID;
     scqr_opts o;
     if (opts)
         o = *opts;
@@ -513,124 +718,105 @@ scqr_status scqr_qr_batched(void *stream, int32_t batch, const int64_t *m, const
         scqr_default_opts(&o);
     if (o.final_gram || o.trace) return SCQR_E_UNSUPPORTED;
     BatchPlan bp;
-    scqr_status st = plan_batch(batch, m, n, o, bp);
+    scqr_status st = plan_batch(batch, m, n, o, tune, bp);
     if (st != SCQR_OK) return st;
-    if (ws_bytes < bp.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return SCQR_E_WORKSPACE;
-    for (int32_t i = 0; i < batch; ++i) {
-        if (!X[i] || !Q[i] || !R[i]) return SCQR_E_INVALID;
-        const size_t xb = mat_bytes(m[i], n[i], n[i]), rb = mat_bytes(n[i], n[i], n[i]);
-        if (Q[i] != X[i] && ranges_overlap(X[i], xb, Q[i], xb)) return SCQR_E_INVALID;
-        if (ranges_overlap(R[i], rb, X[i], xb) || ranges_overlap(R[i], rb, Q[i], xb)) return SCQR_E_INVALID;
-        if (ranges_overlap(ws, bp.total, X[i], xb) || ranges_overlap(ws, bp.total, Q[i], xb) ||
-            ranges_overlap(ws, bp.total, R[i], rb))
-            return SCQR_E_INVALID;
-    }
-
-    // descriptors (instances in class order, then tasks), uploaded to the head of the workspace
-    char *base = static_cast<char *>(ws);
-    std::vector<unsigned char> host(bp.off_blocks, 0);
-    BatchInst *hi = reinterpret_cast<BatchInst *>(host.data() + bp.off_inst);
-    BatchTask *ht = reinterpret_cast<BatchTask *>(host.data() + bp.off_task);
-    const BatchInst *dinst = reinterpret_cast<const BatchInst *>(base + bp.off_inst);
-    const BatchTask *dtask = reinterpret_cast<const BatchTask *>(base + bp.off_task);
+    const BatchArgs a{batch, m, n, X, ldx, Q, ldq, R, ldr, ws, ws_bytes, infos};
+    st = check_batch_args(a, bp);
+    if (st != SCQR_OK) return st;
+    std::vector<unsigned char> host;
     BatchClass cls[kNumClasses];
-    for (int c = 0; c < kNumClasses; ++c) {
-        const int np = kClassNp[c];
-        const int64_t elems = pass_partial_elems(np, false);
-        BatchClass &bc = cls[c];
-        bc.np = np;
-        bc.ninst = bp.cls_first[c + 1] - bp.cls_first[c];
-        bc.ntasks = bp.task_first[c + 1] - bp.task_first[c];
-        bc.insts = dinst + bp.cls_first[c];
-        bc.tasks = dtask + bp.task_first[c];
-        bc.partials = reinterpret_cast<double *>(base + bp.off_part[c]);
-        bc.vec = true;
-        int t = 0;
-        for (int k = bp.cls_first[c]; k < bp.cls_first[c + 1]; ++k) {
-            const int i = bp.order[k];
-            BatchInst &I = hi[k];
-            I.p.m = m[i];
-            I.p.n = (int)n[i];
-            I.p.np = np;
-            I.p.X = X[i];
-            I.p.ldx = n[i];
-            I.p.Q = Q[i];
-            I.p.ldq = n[i];
-            I.p.R = R[i];
-            I.p.ldr = n[i];
-            I.p.zero = 0;
-            char *blk = base + bp.inst_off[i];
-            size_t o2 = 0;
-            I.w.ctl = reinterpret_cast<Ctl *>(blk + o2);
-            o2 += align256(sizeof(Ctl));
-            I.w.Rhist = reinterpret_cast<double *>(blk + o2);
-            o2 += align256(sizeof(double) * np * np * bp.slots);
-            I.w.dhist = reinterpret_cast<double *>(blk + o2);
-            o2 += align256(sizeof(double) * np * bp.slots);
-            I.w.gsum = reinterpret_cast<double *>(blk + o2);
-            o2 += align256(sizeof(double) * elems);
-            if (np > 128) {
-                I.w.G = reinterpret_cast<double *>(blk + o2);
-                o2 += align256(sizeof(double) * np * (np + 1));
-                I.w.Racc[0] = reinterpret_cast<double *>(blk + o2);
-                o2 += align256(sizeof(double) * np * np);
-                I.w.Racc[1] = reinterpret_cast<double *>(blk + o2);
-            }
-            I.w.parts_elems = elems;
-            I.info = infos + i;
-            I.t0 = t;
-            for (int q = 0; q < bp.ntask[i]; ++q, ++t) {
-                BatchTask &T = ht[bp.task_first[c] + t];
-                T.inst = k - bp.cls_first[c];
-                T.r0 = (int64_t)q * bp.task_rows[i];
-                const int64_t r1 = T.r0 + bp.task_rows[i];
-                T.r1 = r1 < m[i] ? r1 : m[i];
-            }
-            I.t1 = t;
-            if ((n[i] & 1) || (reinterpret_cast<uintptr_t>(X[i]) & 15) || (reinterpret_cast<uintptr_t>(Q[i]) & 15))
-                bc.vec = false;
+    build_descriptors(a, bp, host, cls);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = upload(s, ws, host.data(), host.size());
+    if (e == hipSuccess) e = enqueue_batched(s, bp, cls, o);
+    return hip_status(e);
+}
+
+scqr_status scqr_batched_plan_create(int32_t batch, const int64_t *m, const int64_t *n,
+                                     const double *const *X, const int64_t *ldx, double *const *Q,
+                                     const int64_t *ldq, double *const *R, const int64_t *ldr,
+                                     void *ws, size_t ws_bytes, const scqr_opts *opts,
+                                     const scqr_batched_tuning *tune, scqr_info *infos,
+                                     scqr_batched_plan *plan)
+{
+    if (!plan) return SCQR_E_INVALID;
+    *plan = nullptr;
+    if (batch < 1 || !m || !n) return SCQR_E_INVALID;
+    scqr_opts o;
+    if (opts)
+        o = *opts;
+    else
+        scqr_default_opts(&o);
+    if (o.final_gram || o.trace) return SCQR_E_UNSUPPORTED;
+    scqr_batched_plan_s *pl = new (std::nothrow) scqr_batched_plan_s();
+    if (!pl) return SCQR_E_INVALID;
+    pl->o = o;
+    scqr_status st = plan_batch(batch, m, n, o, tune, pl->bp);
+    const BatchArgs a{batch, m, n, X, ldx, Q, ldq, R, ldr, ws, ws_bytes, infos};
+    if (st == SCQR_OK) st = check_batch_args(a, pl->bp);
+    if (st != SCQR_OK) {
+        delete pl;
+        return st;
+    }
+    build_descriptors(a, pl->bp, pl->image, pl->cls);
+    pl->ws = ws;
+    pl->bytes = pl->image.size();
+    *plan = pl;
+    return SCQR_OK;
+}
+
+scqr_status scqr_batched_plan_upload(scqr_batched_plan plan, void *stream)
+{
+    if (!plan) return SCQR_E_INVALID;
+    if (!plan->pinned) {
+        // the plan's pinned copy of the descriptor image, allocated at the first upload
+        if (hipHostMalloc(&plan->pinned, plan->bytes ? plan->bytes : 1, hipHostMallocDefault) != hipSuccess) {
+            plan->pinned = nullptr;
+            return SCQR_E_HIP;
         }
+        if (hipEventCreateWithFlags(&plan->done, hipEventDisableTiming) != hipSuccess) {
+            plan->done = nullptr;
+            return SCQR_E_HIP;
+        }
+        std::memcpy(plan->pinned, plan->image.data(), plan->bytes);
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = upload(s, base, host.data(), host.size());
-
-    SchedParams sp{};
-    sp.schedule = o.schedule;
-    sp.shift_mode = o.shift_mode;
-    sp.precision = o.precision;
-    sp.max_passes = o.max_passes;
-    sp.final_gram = 0;
-    sp.force_bd = o.debug_force_breakdown_pass;
-    sp.zero_shift = o.debug_zero_shift;
-    sp.oblique = 0;
-    sp.custom_alpha = o.custom_alpha;
-    sp.bnorm_user = 0.0;
-    sp.trace = nullptr;
-    sp.info = nullptr;
-    const bool f32 = o.precision == SCQR_PREC_FP32_FIRST;
-    // one launch per class and step; classes of the same step are independent
-    for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) e = launch_init_b(s, cls[c]);
-    for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
-        e = launch_pass_b(s, cls[c], 0, 0, f32, 0);
-        if (e == hipSuccess) e = launch_reduce_b(s, cls[c], 0, 0);
-        if (e == hipSuccess) e = launch_chol_b(s, cls[c], sp, 1, 0);
-    }
-    if (f32) {
-        for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
-            e = launch_pass_b(s, cls[c], 0, -1, false, 0);
-            if (e == hipSuccess) e = launch_reduce_b(s, cls[c], -1, 0);
-            if (e == hipSuccess) e = launch_chol_b(s, cls[c], sp, 1, 1);
-        }
-    }
-    for (int pass = 1; pass <= bp.P && e == hipSuccess; ++pass) {
-        for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
-            e = launch_pass_b(s, cls[c], 1, pass, false, 0);
-            if (e == hipSuccess) e = launch_reduce_b(s, cls[c], pass, 0);
-            if (e == hipSuccess && pass < bp.P) e = launch_chol_b(s, cls[c], sp, pass + 1, 0);
-        }
-    }
-    for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) e = launch_finalize_b(s, cls[c]);
+    hipError_t e = hipMemcpyAsync(plan->ws, plan->pinned, plan->bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(plan->done, s);
+    if (e == hipSuccess) plan->uploaded = true;
     return hip_status(e);
+}
+
+scqr_status scqr_batched_plan_run(scqr_batched_plan plan, void *stream)
+{
+    if (!plan) return SCQR_E_INVALID;
+    if (!plan->uploaded) return SCQR_E_INVALID;
+    return hip_status(enqueue_batched(static_cast<hipStream_t>(stream), plan->bp, plan->cls, plan->o));
+}
+
+scqr_status scqr_batched_plan_destroy(scqr_batched_plan plan)
+{
+    if (!plan) return SCQR_OK;
+    scqr_status st = SCQR_OK;
+    if (plan->done) {
+        if (plan->uploaded && hipEventSynchronize(plan->done) != hipSuccess) st = SCQR_E_HIP;
+        (void)hipEventDestroy(plan->done);
+    }
+    if (plan->pinned) (void)hipHostFree(plan->pinned);
+    delete plan;
+    return st;
+}
+
+scqr_status scqr_batched_plan_tuning(scqr_batched_plan plan, scqr_batched_tuning *tune, int32_t *ntasks)
+{
+    if (!plan || !tune) return SCQR_E_INVALID;
+    std::memset(tune, 0, sizeof(*tune));
+    for (int c = 0; c < kNumClasses; ++c) {
+        tune->rows_per_task[c] = plan->bp.rows_per_task[c];
+        tune->panel_rows[c] = plan->bp.panel_rows[c];
+        if (ntasks) ntasks[c] = plan->bp.task_first[c + 1] - plan->bp.task_first[c];
+    }
+    return SCQR_OK;
 }
 
 scqr_status scqr_backward_workspace_bytes(int64_t m, int64_t n, size_t *bytes)

@@ -182,8 +182,11 @@ __device__ double power_lambda_regs(const double *G, int S, int n, double *v)
         const double vy = wave_sum_dpp(vi * y);
         const double yy = wave_sum_dpp(y * y);
         const double prev = lam;
+        if (!(yy > 0.0)) {
+            lam = -1.0;  // G v = 0: the caller falls back to the trace
+            break;
+        }
         lam = vy;
-        if (!(yy > 0.0)) break;
         const double inv = 1.0 / sqrt(yy);
         vi = y * inv;
         wave_sync_c();
@@ -315,8 +318,11 @@ __device__ double power_lambda_block(const double *G, int S, int n, double *v, d
         const double vy = (red[0] + red[2]) + (red[4] + red[6]);
         const double yy = (red[1] + red[3]) + (red[5] + red[7]);
         const double prev = lam;
+        if (!(yy > 0.0)) {
+            lam = -1.0;  // G v = 0: the caller falls back to the trace
+            break;
+        }
         lam = vy;
-        if (!(yy > 0.0)) break;
         vi = y * (1.0 / sqrt(yy));
         if (h == 0 && row < NP) v[row] = vi;
         __syncthreads();
@@ -329,6 +335,8 @@ __device__ double power_lambda_block(const double *G, int S, int n, double *v, d
 // ||X||_2^2 estimate (normest's rule: Rayleigh-quotient power iteration on the Gram from the
 // start vector 1/sqrt(n), stopped at a relative change <= 1e-6 or after 100 iterations; a lower
 // bound of lambda_max).  NP <= 64: the first wave alone, the result broadcast through LDS.
+// Returns -1 when an iterate falls in the null space of the computed Gram (G v = 0 in
+// floating point); the caller then takes the trace instead (||X||_F^2, Section 4.1).
 template <int NP>
 __device__ __forceinline__ double power_lambda(const double *G, int S, int n, double *v, double *red)
 {
@@ -530,11 +538,11 @@ __device__ __forceinline__ int chol_inplace(double *G, int S, int n, double s, d
 }
 
 __device__ double shift_value(const SchedParams &sp, int64_t m, int n, double norm2sq,
-                              double bfac, bool oblique, bool f32pass)
+                              double bfac, bool oblique, bool f32pass, int f32_chain)
 {
     const double dm = (double)m, dn = (double)n;
     if (f32pass)
-        return 11.0 * ((kF32Chain + 2.0) * dn * kU32 + dn * (dn + 1.0) * kU64) * norm2sq;
+        return 11.0 * (((double)f32_chain + 2.0) * dn * kU32 + dn * (dn + 1.0) * kU64) * norm2sq;
     double c;
     if (sp.shift_mode == SCQR_SHIFT_SMALL)
         c = kU64;
@@ -583,6 +591,15 @@ __device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const
     block_sum3(badd, dev, tr, red);
     const bool bad = badd > 0.0;
     dev = sqrt(dev);
+    if (bad && f32pass) {
+        // the binary32 Gram overflowed (or X holds a NaN / Inf): redo the first pass in binary64,
+        // whose own finiteness test decides the status
+        if (threadIdx.x == 0) {
+            ctl->redo_fp64 = 1;
+            info->fell_back_fp64 = 1;
+        }
+        return;
+    }
     if (bad) {
         if (threadIdx.x == 0) {
             ctl->active = 0;
@@ -601,23 +618,27 @@ __device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const
         }
     }
 
-    // norm estimate used by a shift of this pass
+    // norm estimate used by a shift of this pass: the power iteration's lambda_max estimate,
+    // raised to max_i a_ii (also a lower bound of lambda_max), or the trace ||.||_F^2 (Section
+    // 4.1 allows the Frobenius norm) when the shift mode asks for it or the iteration met G v = 0
     auto norm_estimate = [&]() -> double {
         const double *Gn = G;
+        double trn = tr;
         if (obl_first) {
             // ||X||_2 of (eq:finds2B) is the Euclidean norm: Gram X^T X assembled in w.Ge
             double b2 = 0.0, d2 = 0.0, t2 = 0.0;
             assemble<NP>(w, n, E, false, w.Ge, S, b2, d2, t2);
-            if (sp.shift_mode == SCQR_SHIFT_FRO) {
-                double t2 = 0.0;
-                for (int i = threadIdx.x; i < n; i += blockDim.x) t2 += w.Ge[i * S + i];
-                return block_sum(t2, red);
-            }
+            double t3 = 0.0;
+            for (int i = threadIdx.x; i < n; i += blockDim.x) t3 += w.Ge[i * S + i];
+            trn = block_sum(t3, red);
             Gn = w.Ge;
-        } else if (sp.shift_mode == SCQR_SHIFT_FRO) {
-            return tr;
         }
-        return power_lambda<NP>(Gn, S, n, vbuf, red);
+        if (sp.shift_mode == SCQR_SHIFT_FRO) return trn;
+        const double lam = power_lambda<NP>(Gn, S, n, vbuf, red);
+        if (!(lam >= 0.0)) return trn;
+        double dmax = 0.0;
+        for (int i = 0; i < n; ++i) dmax = Gn[i * S + i] > dmax ? Gn[i * S + i] : dmax;
+        return lam > dmax ? lam : dmax;
     };
     double bfac = 1.0;
     if (obl_first) {
@@ -646,7 +667,7 @@ __device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const
     for (int attempt = 0; attempt < 2; ++attempt) {
         if (try_shift) {
             nrm = norm_estimate();
-            s = shift_value(sp, p.m, n, nrm, bfac, oblique, f32pass);
+            s = shift_value(sp, p.m, n, nrm, bfac, oblique, f32pass, f32_chain_rows(NP));
             if (sp.zero_shift) s = 0.0;
             shifted = 1;
             if (f32pass && s > 0.01 * nrm) {

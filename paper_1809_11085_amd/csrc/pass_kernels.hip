@@ -48,7 +48,8 @@ __device__ __forceinline__ void wave_sync()
 // The solved panel then feeds the FP64 MFMA Gram (all upper 16x16 tiles in registers).
 //   MODE 0: Gram of X only.  MODE 1: TRSM + Gram.  MODE 2: TRSM only.  MODE 3: the transposed
 //   solve x R~^T = y row by row (back substitution in blocked order, for the QR adjoint).
-//   F32: Gram in binary32 MFMA, flushed to binary64 after every 64-row chain (MODE 0 only).
+//   F32: Gram in binary32 MFMA, each panel (one chain of f32_chain_rows(NP) = PR rows) added to the
+//        binary64 tiles after the panel (MODE 0 only).
 //   VEC: n even, even leading dimensions and 16-byte aligned X, Q (pairs of doubles per access).
 //   PR: rows per panel (32: 8 waves per workgroup, 64: 4 waves).
 //   BATCH false: one problem; the waves of all workgroups interleave over its panels.
@@ -91,6 +92,7 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
     constexpr int LDSZ = (WAVES * PANEL > T * 256) ? WAVES * PANEL : T * 256;
     constexpr int PP = PR * NP / 2 / 64;  // double pairs per lane per panel
     static_assert((PR * NP / 2) % 64 == 0, "panel must split evenly over a wave");
+    static_assert(!F32 || PR == f32_chain_rows(NP), "a binary32 chain is one panel");
     constexpr int BL = (MODE >= 1 && NOFF > 0) ? NOFF * 4 * 64 : 1;
     __shared__ __attribute__((aligned(16))) double lds[LDSZ];
     __shared__ double bl[BL];
@@ -769,6 +771,7 @@ k_gram_wide(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
     constexpr int S = lds_stride_gram(NP);
     constexpr int PP = PR * NP / 2 / NTH;  // double pairs per thread per panel
     static_assert(PP >= 1 && (PR * NP / 2) % NTH == 0, "panel must split over the workgroup");
+    static_assert(!F32 || PR == f32_chain_rows(NP), "a binary32 chain is one panel");
     constexpr int64_t E = (int64_t)T * 256;
     __shared__ __attribute__((aligned(16))) double xs[(PR + 2 * H) * S];
     __shared__ __attribute__((aligned(16))) double ys[OBL ? PR * S : 1];
@@ -1271,7 +1274,7 @@ k_trsm_big_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__ 
 //        and (B x)_k = off_{k-1} x_{k-1} + diag_k x_k + off_k x_{k+1} is formed on the fly.
 //   EUC: with OBL, also the Euclidean X^T X (second half of the partial) and the per-workgroup
 //        Gershgorin maximum of B (first-pass shift of equation (eq:finds2B)).
-//   F32: binary32 MFMA, flushed to binary64 after every 64 rows.
+//   F32: binary32 MFMA, flushed to binary64 after every f32_chain_rows(NP) rows.
 //   The workgroup takes the 16-row panels [p0, p1) and writes its partial to part_out (and its
 //   Gershgorin maximum to *bmax_out).
 template <int NP, int WAVES, bool OBL, bool EUC, bool F32>
@@ -1382,7 +1385,7 @@ gram_lds_body(const Problem &p, double *__restrict__ part_out, double *__restric
         }
         if (F32) {
             chain += PR;
-            if (chain >= kF32Chain || pn + 1 == p1) {
+            if (chain >= f32_chain_rows(NP) || pn + 1 == p1) {
                 chain = 0;
 #pragma unroll
                 for (int u = 0; u < TPW; ++u) {
@@ -1667,10 +1670,14 @@ static hipError_t launch_gram_wide(hipStream_t s, const Problem &p, const Work &
     else if (obl)
         hipLaunchKernelGGL((k_gram_wide<NP, true, false, false, false>), grid, block, 0, s, p, w.partials, w.bmax,
                            w.ctl, pass, final_gram, ni, nt);
-    else if (f32)
-        hipLaunchKernelGGL((k_gram_wide<NP, false, false, true, false>), grid, block, 0, s, p, w.partials, w.bmax,
-                           w.ctl, pass, final_gram, ni, nt);
-    else
+    else if (f32) {
+        // the binary32 Gram of np <= 64 is formed by k_pass_tile
+        if constexpr (NP == 128)
+            hipLaunchKernelGGL((k_gram_wide<NP, false, false, true, false>), grid, block, 0, s, p, w.partials,
+                               w.bmax, w.ctl, pass, final_gram, ni, nt);
+        else
+            return hipErrorInvalidValue;
+    } else
         hipLaunchKernelGGL((k_gram_wide<NP, false, false, false, false>), grid, block, 0, s, p, w.partials, w.bmax,
                            w.ctl, pass, final_gram, ni, nt);
     return hipGetLastError();
@@ -1789,14 +1796,13 @@ hipError_t launch_reduce(hipStream_t s, const Work &w, int pass, int64_t elems, 
 }
 
 // ---- batched launchers -------------------------------------------------------------------
-template <int NP, bool VEC>
+template <int NP, bool VEC, int PR>
 static void launch_small_b(hipStream_t s, const BatchClass &c, int mode, int pass, bool f32, int final_gram)
 {
-    constexpr int PR = kPanelRows;
     dim3 grid((unsigned)c.ntasks), block(PR == 64 ? 256 : 512);
-    if (mode == 0 && f32)
-        hipLaunchKernelGGL((k_pass_tile<NP, 0, true, VEC, PR, true>), grid, block, 0, s, Problem{}, nullptr, nullptr, nullptr,
-                           c.partials, nullptr, pass, final_gram, c.insts, c.tasks);
+    if (mode == 0 && f32)  // the binary32 chain is one 32-row panel, whatever the tuning
+        hipLaunchKernelGGL((k_pass_tile<NP, 0, true, VEC, kPanelRows, true>), grid, dim3(512), 0, s, Problem{}, nullptr,
+                           nullptr, nullptr, c.partials, nullptr, pass, final_gram, c.insts, c.tasks);
     else if (mode == 0)
         hipLaunchKernelGGL((k_pass_tile<NP, 0, false, VEC, PR, true>), grid, block, 0, s, Problem{}, nullptr, nullptr, nullptr,
                            c.partials, nullptr, pass, final_gram, c.insts, c.tasks);
@@ -1808,10 +1814,17 @@ static void launch_small_b(hipStream_t s, const BatchClass &c, int mode, int pas
 template <int NP>
 static void launch_small_bv(hipStream_t s, const BatchClass &c, int mode, int pass, bool f32, int final_gram)
 {
-    if (c.vec)
-        launch_small_b<NP, true>(s, c, mode, pass, f32, final_gram);
-    else
-        launch_small_b<NP, false>(s, c, mode, pass, f32, final_gram);
+    if (c.vec) {
+        if (c.pr == 64)
+            launch_small_b<NP, true, 64>(s, c, mode, pass, f32, final_gram);
+        else
+            launch_small_b<NP, true, 32>(s, c, mode, pass, f32, final_gram);
+    } else {
+        if (c.pr == 64)
+            launch_small_b<NP, false, 64>(s, c, mode, pass, f32, final_gram);
+        else
+            launch_small_b<NP, false, 32>(s, c, mode, pass, f32, final_gram);
+    }
 }
 
 template <int NP, int WAVES>

@@ -10,7 +10,6 @@ namespace scqr {
 
 constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53
 constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
-constexpr int kF32Chain = 64;                     // rows per binary32 accumulation chain
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
@@ -62,6 +61,13 @@ __host__ __device__ inline void acc32_rc(int e, int &i, int &j)
     i = 4 * (l >> 4) + r;
     j = l & 15;
 }
+
+// FP32-first option: rows accumulated in one binary32 MFMA chain of the first Gram before the
+// chain's sum is added to the binary64 tiles, by padded width.  It is one panel of the kernel
+// that forms that Gram (k_pass_tile: 32 rows for np <= 64; k_gram_wide: 64 rows at np = 128,
+// 16 rows at np = 256; k_gram_lds flushes at the same counts), and the binary32 shift
+// s32 = 11 ((k + 2) n u32 + n (n + 1) u) ||X||_2^2 takes this k.
+__host__ __device__ constexpr int f32_chain_rows(int np) { return np <= 64 ? 32 : (np == 128 ? 64 : 16); }
 
 // Padded width used by the kernels: the smallest of 16, 32, 64, 128, 256 that holds n.
 inline int padded_n(int64_t n)
@@ -196,6 +202,7 @@ struct BatchClass {
     const BatchTask *tasks;   // device
     double *partials;         // ntasks x pass_partial_elems(np, false)
     bool vec;                 // every instance allows 16-byte accesses of X and Q
+    int pr;                   // np <= 64: rows per wave panel of the fused pass (32 or 64)
 };
 hipError_t launch_init_b(hipStream_t s, const BatchClass &c);
 hipError_t launch_pass_b(hipStream_t s, const BatchClass &c, int mode, int pass, bool fp32_gram,

