@@ -147,6 +147,26 @@ scqr_status scqr_qr(void *stream, int64_t m, int64_t n, const double *X, int64_t
                     void *ws, size_t ws_bytes, const scqr_opts *opts, scqr_info *info);
 
 /*
+ * scqr_qr without a workspace argument and without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, results and status codes are those of scqr_qr; the
+ * workspace is a static device array of SCQR_NOALLOC_SCRATCH_BYTES bytes inside the library
+ * (one per GPU, held until the process ends; its device address is looked up once per device
+ * on the first call there, with that device current).  Shapes whose workspace
+ * (scqr_workspace_bytes) exceeds it return SCQR_E_WORKSPACE before anything is enqueued: at
+ * most n <= 64 for any m, Euclidean or tridiagonal B, on a GPU of up to 256 compute units.  The
+ * call allocates nothing (no hipMalloc, no library allocation) and enqueues the same kernels
+ * as scqr_qr, with the same results bit for bit.  Every call on one GPU uses the same scratch:
+ * calls that overlap in time on one GPU (other streams, other host threads) race and must be
+ * serialized by the caller.  Nothing in the scratch needs to start at zero (the first kernel
+ * of a call initialises the control state).
+ */
+#define SCQR_NOALLOC_SCRATCH_BYTES (16u << 20)
+scqr_status scqr_qr_noalloc(void *stream, int64_t m, int64_t n, const double *X, int64_t ldx,
+                            const scqr_spd_op *B, double *Q, int64_t ldq, double *R, int64_t ldr,
+                            const scqr_opts *opts, scqr_info *info);
+
+/*
  * Gram matrix G = X^T X (equation (eq:gram)), or X^T B X for tridiagonal B (Algorithm 4 line
  * 1): the split-m SYRK of one pass with a fixed-order reduction across workgroups.  G is
  * n x n, ldg >= n, both triangles written (the upper triangle mirrored).

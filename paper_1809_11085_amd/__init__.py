@@ -112,6 +112,9 @@ def lib():
         L.scqr_qr.argtypes = [P, I64, I64, P, I64, ctypes.POINTER(_SpdOp), P, I64, P, I64, P, SZ,
                               ctypes.POINTER(_Opts), P]
         L.scqr_qr.restype = st
+        L.scqr_qr_noalloc.argtypes = [P, I64, I64, P, I64, ctypes.POINTER(_SpdOp), P, I64, P, I64,
+                                      ctypes.POINTER(_Opts), P]
+        L.scqr_qr_noalloc.restype = st
         L.scqr_gram.argtypes = [P, I64, I64, P, I64, ctypes.POINTER(_SpdOp), P, I64, P, SZ]
         L.scqr_gram.restype = st
         L.scqr_trsm.argtypes = [P, I64, I64, P, I64, P, I64, P, I64, P, SZ]
@@ -295,6 +298,30 @@ def qr(X: torch.Tensor, B=None, *, inplace=False, check=True, trace=False, **opt
     if info.status != OK and mode == "raise":
         raise ScqrError(info.status, f"scqr_qr: {status_string(info.status)}", info, (Q, R))
     return Q, R, info
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20
+
+
+def qr_noalloc(X: torch.Tensor, Q: torch.Tensor, R: torch.Tensor, info: torch.Tensor, B=None, **opts):
+    """scqr_qr_noalloc: the factorization into caller-allocated Q (may be X), R and a device
+    info record (uint8 tensor of INFO_BYTES), with the library's static device scratch as the
+    workspace.  Nothing is allocated on the device and nothing is synchronized; decode the
+    record with ``decode_info(info)``.  Shapes whose workspace exceeds the scratch
+    (NOALLOC_SCRATCH_BYTES) raise ScqrError with SCQR_E_WORKSPACE."""
+    m, n = X.shape
+    xp, ldx = _mat(X, "X")
+    qp, ldq = _mat(Q, "Q")
+    rp, ldr = _mat(R, "R")
+    if Q.shape != X.shape or R.shape != (n, n):
+        raise ValueError("Q must be m x n and R n x n")
+    if info.dtype != torch.uint8 or info.numel() < INFO_BYTES or not info.is_cuda:
+        raise TypeError(f"info must be a CUDA uint8 tensor of at least {INFO_BYTES} bytes")
+    o = _opts(**opts)
+    spd = _spd(B, m) if B is not None else None
+    _check(lib().scqr_qr_noalloc(_stream(X.device), m, n, xp, ldx, ctypes.byref(spd) if spd else None,
+                                 qp, ldq, rp, ldr, ctypes.byref(o), info.data_ptr()), "scqr_qr_noalloc")
+    return Q, R
 
 
 def gram(X: torch.Tensor, B=None) -> torch.Tensor:
@@ -562,3 +589,4 @@ def profile_read(capacity: int = 1 << 16) -> list:
 
 def build_info() -> str:
     return lib().scqr_build_info().decode()
+

@@ -541,9 +541,15 @@ scqr_status scqr_workspace_bytes(int64_t m, int64_t n, const scqr_spd_op *B, con
     return SCQR_OK;
 }
 
-scqr_status scqr_qr(void *stream, int64_t m, int64_t n, const double *X, int64_t ldx,
-                    const scqr_spd_op *B, double *Q, int64_t ldq, double *R, int64_t ldr, void *ws,
-                    size_t ws_bytes, const scqr_opts *opts, scqr_info *info)
+}  // extern "C"
+
+namespace {
+
+// Validation and enqueue sequence shared by scqr_qr (caller's workspace) and scqr_qr_noalloc
+// (the library's static device scratch).
+scqr_status qr_enqueue(void *stream, int64_t m, int64_t n, const double *X, int64_t ldx,
+                       const scqr_spd_op *B, double *Q, int64_t ldq, double *R, int64_t ldr, void *ws,
+                       size_t ws_bytes, const scqr_opts *opts, scqr_info *info)
 {
     if (n < 1 || m < n) return SCQR_E_INVALID;
     if (n > SCQR_MAX_N) return SCQR_E_UNSUPPORTED;
@@ -627,6 +633,61 @@ scqr_status scqr_qr(void *stream, int64_t m, int64_t n, const double *X, int64_t
     if (e == hipSuccess) e = launch_finalize_r(s, p, w, P);
     if (e == hipSuccess && fg) e = launch_final_omega(s, p, w, sp);
     return hip_status(e);
+}
+
+// Device scratch of the no-allocation entry point: one copy per GPU, held until the process
+// ends.  In host code `scratch` names a host-side stand-in, never the device memory: the
+// device address comes from hipGetSymbolAddress, taken once per device with that device
+// current, and only that address is passed to kernels.
+constexpr size_t kScratchBytes = (size_t)SCQR_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+scqr_status scratch_for_current_device(void **ptr)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return SCQR_E_HIP;
+    if (dev >= kMaxDevices) return SCQR_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SCQR_E_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return SCQR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+scqr_status scqr_qr(void *stream, int64_t m, int64_t n, const double *X, int64_t ldx,
+                    const scqr_spd_op *B, double *Q, int64_t ldq, double *R, int64_t ldr, void *ws,
+                    size_t ws_bytes, const scqr_opts *opts, scqr_info *info)
+{
+    return qr_enqueue(stream, m, n, X, ldx, B, Q, ldq, R, ldr, ws, ws_bytes, opts, info);
+}
+
+scqr_status scqr_qr_noalloc(void *stream, int64_t m, int64_t n, const double *X, int64_t ldx,
+                            const scqr_spd_op *B, double *Q, int64_t ldq, double *R, int64_t ldr,
+                            const scqr_opts *opts, scqr_info *info)
+{
+    // shape and pointer checks first: invalid calls return without any HIP call
+    if (n < 1 || m < n) return SCQR_E_INVALID;
+    if (n > SCQR_MAX_N) return SCQR_E_UNSUPPORTED;
+    if (!X || !Q || !R || !info) return SCQR_E_INVALID;
+    if (ldx < n || ldq < n || ldr < n) return SCQR_E_INVALID;
+    scqr_status st = check_B(B, m);
+    if (st != SCQR_OK) return st;
+    if (opts && (st = check_opts(opts)) != SCQR_OK) return st;
+    if (layout(m, n, is_oblique(B)).total > kScratchBytes) return SCQR_E_WORKSPACE;
+    void *ws = nullptr;
+    st = scratch_for_current_device(&ws);
+    if (st != SCQR_OK) return st;
+    return qr_enqueue(stream, m, n, X, ldx, B, Q, ldq, R, ldr, ws, kScratchBytes, opts, info);
 }
 
 scqr_status scqr_gram(void *stream, int64_t m, int64_t n, const double *X, int64_t ldx,

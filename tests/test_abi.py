@@ -242,3 +242,31 @@ def test_workspace_sizes_of_batched_and_adjoint(L):
     assert L.scqr_backward_workspace_bytes(1000, 0, ctypes.byref(sz)) == scqr.E_INVALID
     assert L.scqr_backward_workspace_bytes(1000, 257, ctypes.byref(sz)) == scqr.E_INVALID
     assert L.scqr_backward_workspace_bytes(1000, 8, None) == scqr.E_INVALID
+
+
+def test_noalloc_validation_without_device(L):
+    # argument errors and shapes whose workspace exceeds the static scratch are rejected before
+    # any HIP call
+    import paper_1809_11085_amd as scqr
+    P = 0x100000
+    info = ctypes.c_void_p(P)
+    assert L.scqr_qr_noalloc(None, 5, 10, P, 10, None, P, 10, P, 10, None, info) == scqr.E_INVALID
+    assert L.scqr_qr_noalloc(None, 5000, 300, P, 300, None, P, 300, P, 300, None, info) == scqr.E_UNSUPPORTED
+    assert L.scqr_qr_noalloc(None, 5000, 30, P, 20, None, P, 30, P, 30, None, info) == scqr.E_INVALID
+    assert L.scqr_qr_noalloc(None, 5000, 30, P, 30, None, P, 30, P, 30, None, None) == scqr.E_INVALID
+    o = scqr._Opts()
+    L.scqr_default_opts(ctypes.byref(o))
+    o.schedule = 9
+    assert L.scqr_qr_noalloc(None, 5000, 30, P, 30, None, P, 30, P, 30, ctypes.byref(o), info) == scqr.E_INVALID
+    # n = 128 and 256 need more than the scratch holds
+    for n in (128, 256):
+        assert L.scqr_qr_noalloc(None, 1 << 20, n, P, n, None, 0x900000000, n, 0x800000000, n, None,
+                                 info) == scqr.E_WORKSPACE
+    # every shape up to n = 64 fits, Euclidean or oblique
+    sz = ctypes.c_size_t()
+    spd = scqr._SpdOp()
+    spd.kind = 1
+    for n in (1, 16, 33, 64):
+        for Bp in (None, ctypes.byref(spd)):
+            assert L.scqr_workspace_bytes(1 << 30, n, Bp, None, ctypes.byref(sz)) == scqr.OK
+            assert sz.value <= scqr.NOALLOC_SCRATCH_BYTES
