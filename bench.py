@@ -108,6 +108,48 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
     print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}))
 
 
+def peaks():
+    """Device ceilings measured with the library's yardstick kernels (scqr_peak_*): streaming
+    copy, read and write of 2 GiB (the size of X at m = 2^22, n = 64) over launch widths and
+    per-thread unrolls, and the sustained FP64 MFMA 16x16x4 and FP64 FMA rates.  Prints one
+    JSON line with the best of each and every measurement."""
+    import torch
+
+    import paper_1809_11085_amd as scqr
+
+    torch.cuda.set_device(0)
+    nbytes = 1 << 31
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    sink = torch.empty(16384 * 256, dtype=torch.float64, device="cuda")
+    rows = []
+    for grid in (1024, 2048, 4096):
+        for v in range(8):
+            ms = _time_ms(lambda: scqr.peak("copy", src, dst, variant=v, grid=grid), reps=5)
+            rows.append({"kind": "copy", "grid": grid, "unroll": 1 << (v & 3), "nt_store": bool(v & 4),
+                         "GB/s": round(2 * nbytes / ms / 1e6, 1)})
+            ms = _time_ms(lambda: scqr.peak("write", dst, variant=v, grid=grid), reps=5)
+            rows.append({"kind": "write", "grid": grid, "unroll": 1 << (v & 3), "nt_store": bool(v & 4),
+                         "GB/s": round(nbytes / ms / 1e6, 1)})
+        for v in range(4):
+            ms = _time_ms(lambda: scqr.peak("read", src, sink, variant=v, grid=grid), reps=5)
+            rows.append({"kind": "read", "grid": grid, "unroll": 1 << v, "GB/s": round(nbytes / ms / 1e6, 1)})
+    iters = 4000
+    for grid in (1024, 2048, 4096):
+        ms = _time_ms(lambda: scqr.peak("mfma", sink, grid=grid, iters=iters), reps=3)
+        fl = grid * 4 * iters * 8 * 2048
+        rows.append({"kind": "fp64_mfma_16x16x4", "grid": grid, "TFLOP/s": round(fl / ms / 1e9, 2)})
+        ms = _time_ms(lambda: scqr.peak("fma", sink, grid=grid, iters=iters), reps=3)
+        fl = grid * 256 * iters * 8 * 2
+        rows.append({"kind": "fp64_fma", "grid": grid, "TFLOP/s": round(fl / ms / 1e9, 2)})
+    best = {}
+    for r in rows:
+        key, val = r["kind"], r.get("GB/s", r.get("TFLOP/s"))
+        if key not in best or val > best[key]["value"]:
+            best[key] = {"value": val, "unit": "GB/s" if "GB/s" in r else "TFLOP/s", "config": r}
+    print(json.dumps({"peaks": best, "all": rows, "device": torch.cuda.get_device_name(0)}), flush=True)
+
+
 def _time_ms(fn, reps=3, warmup=1):
     """Median over reps of the HIP-event time of fn() on the current stream (ms)."""
     import torch
@@ -170,6 +212,68 @@ def extra_c3(scqr, synth):
     return res
 
 
+def _fp64_metrics(X, Q, R):
+    """omega_2 = ||Q^T Q - I||_2 and rho = ||X - QR||_F / ||X||_F in plain binary64 (BLAS
+    products; their rounding, about sqrt(m) u, stays far below the 1e-13 bar)."""
+    import numpy as np
+
+    n = Q.shape[1]
+    om = float(np.max(np.abs(np.linalg.eigvalsh(Q.T @ Q - np.eye(n)))))
+    rho = float(np.linalg.norm(X - Q @ R) / np.linalg.norm(X))
+    return om, rho
+
+
+def c4_accuracy(scqr, Xs, fp64, mixed, sample_every=16):
+    """Per-instance accuracy of the two c4 runs (outside the timed region): omega_2, rho and
+    passes for every instance of both runs, the relative R difference between the FP32-first and
+    the FP64 run for every instance, and the relative R error of both runs against the CPU
+    oracle's FP64 factorization on every sample_every-th instance (about 32 of 512)."""
+    import numpy as np
+
+    import oracle
+
+    out = {}
+    Rf = []
+    Xh_all = [X.cpu().numpy() for X in Xs]
+    for name, (Qs, Rs, infos) in (("fp64", fp64), ("fp32_first", mixed)):
+        om, rho, rerr = [], [], []
+        for i, Xh in enumerate(Xh_all):
+            Qh, Rh = Qs[i].cpu().numpy(), Rs[i].cpu().numpy()
+            a, b = _fp64_metrics(Xh, Qh, Rh)
+            om.append(a)
+            rho.append(b)
+            if name == "fp64":
+                Rf.append(Rh)
+            else:
+                rerr.append(float(np.linalg.norm(Rh - Rf[i]) / np.linalg.norm(Rf[i])))
+        passes = [int(x.passes) for x in infos]
+        d = {"omega2_max": max(om), "omega2_median": float(np.median(om)), "rho_max": max(rho),
+             "rho_median": float(np.median(rho)), "ok": sum(1 for x in infos if x.status == scqr.OK),
+             "within_1e-13": sum(1 for a, b in zip(om, rho) if a <= 1e-13 and b <= 1e-13),
+             "passes_hist": {str(k): passes.count(k) for k in sorted(set(passes))}}
+        if rerr:
+            d["R_rel_diff_vs_fp64_run_max"] = max(rerr)
+            d["R_rel_diff_vs_fp64_run_median"] = float(np.median(rerr))
+            d["fell_back_fp64"] = sum(1 for x in infos if x.fell_back_fp64)
+        out[name] = d
+    # against the oracle on a sample covering every width and the whole kappa range
+    sample = list(range(0, len(Xs), sample_every))
+    err = {"fp64": [], "fp32_first": []}
+    kap = []
+    for i in sample:
+        ro = oracle.scqr(Xh_all[i], schedule=oracle.ADAPTIVE)
+        nr = np.linalg.norm(ro.R)
+        for name, (Qs, Rs, infos) in (("fp64", fp64), ("fp32_first", mixed)):
+            err[name].append(float(np.linalg.norm(Rs[i].cpu().numpy() - ro.R) / nr))
+        kap.append(float(np.linalg.cond(ro.R)))
+    for name in err:
+        e = np.array(err[name])
+        out[name]["R_rel_err_vs_oracle_sample"] = {
+            "instances": len(sample), "max": float(e.max()), "median": float(np.median(e)),
+            "max_over_kappa_u": float(np.max(e / (np.array(kap) * 2.0 ** -53)))}
+    return out
+
+
 def extra_c4(scqr, synth):
     import torch
 
@@ -203,8 +307,6 @@ def extra_c4(scqr, synth):
     res["ok"] = sum(1 for i in infos if i.status == scqr.OK)
     res["passes_hist"] = {str(k): passes.count(k) for k in sorted(set(passes))}
     res["passes_equal_loop"] = sum(1 for a, b in zip(passes, passes_loop) if a == b)
-    del bp
-    torch.cuda.empty_cache()
     bm = scqr.BatchedPlan(shapes, "cuda", precision="fp32_first")
     ms_m = _time_ms(lambda: bm.run(Xs), reps=5)
     im = bm.read_infos()
@@ -212,7 +314,10 @@ def extra_c4(scqr, synth):
     res["speedup_mixed_vs_fp64_batched"] = round(ms_b / ms_m, 3)
     res["mixed_ok"] = sum(1 for i in im if i.status == scqr.OK)
     res["mixed_fell_back"] = sum(1 for i in im if i.fell_back_fp64)
-    del bm, Xs
+    t0 = time.perf_counter()
+    res["accuracy"] = c4_accuracy(scqr, Xs, (bp.Qs, bp.Rs, infos), (bm.Qs, bm.Rs, im))
+    log(f"[bench] c4 accuracy of both runs in {time.perf_counter() - t0:.1f} s")
+    del bp, bm, Xs
     torch.cuda.empty_cache()
     return res
 
@@ -360,6 +465,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--peaks", action="store_true",
+                    help="measure the device ceilings (copy, read, write, FP64 MFMA, FP64 FMA) and exit")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="write profiles/<kernel>_<workload>.md and _counters.json from the rocprofv3 "
@@ -381,6 +488,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.peaks:
+        peaks()
         return
     if args.summarize_profile:
         summarize_profile(args.summarize_profile, args.workload)

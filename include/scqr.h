@@ -278,6 +278,26 @@ typedef struct {
 scqr_status scqr_profile_enable(int32_t on);
 scqr_status scqr_profile_read(scqr_kernel_stat *stats, int32_t capacity, int32_t *count);
 
+/*
+ * Device ceilings for the roofline figures (no part of a factorization).  All pointers are
+ * device pointers, 16-byte aligned; nbytes a positive multiple of 16; grid = workgroups of 256
+ * threads (0 selects 2048).  Time them with events on `stream`.
+ *   scqr_peak_copy   dst[i] = src[i] over nbytes; variant bits 0-1 select 1, 2, 4 or 8
+ *                    16-byte chunks per thread and step, bit 2 non-temporal stores.
+ *   scqr_peak_read   reads nbytes; sink receives grid * 256 doubles (per-thread sums).
+ *   scqr_peak_write  writes nbytes (variant as for the copy).
+ *   scqr_peak_fp64   kind 0: FP64 MFMA 16x16x4 (2048 flops per instruction), kind 1: FP64
+ *                    FMA (2 flops per lane): grid workgroups of four waves, each running
+ *                    `iters` rounds of 8 independent instructions; sink as for the read.
+ * Return SCQR_E_INVALID for bad arguments (nothing enqueued), SCQR_E_HIP on a launch error.
+ */
+scqr_status scqr_peak_copy(void *stream, const void *src, void *dst, int64_t nbytes, int32_t variant,
+                           int32_t grid);
+scqr_status scqr_peak_read(void *stream, const void *src, int64_t nbytes, int32_t variant, int32_t grid,
+                           double *sink);
+scqr_status scqr_peak_write(void *stream, void *dst, int64_t nbytes, int32_t variant, int32_t grid);
+scqr_status scqr_peak_fp64(void *stream, int32_t kind, int32_t iters, int32_t grid, double *sink);
+
 /* Build identification: a static string naming the target architecture and version. */
 const char *scqr_build_info(void);
 

@@ -115,6 +115,14 @@ def lib():
         L.scqr_qr_noalloc.argtypes = [P, I64, I64, P, I64, ctypes.POINTER(_SpdOp), P, I64, P, I64,
                                       ctypes.POINTER(_Opts), P]
         L.scqr_qr_noalloc.restype = st
+        L.scqr_peak_copy.argtypes = [P, P, P, I64, I32, I32]
+        L.scqr_peak_copy.restype = st
+        L.scqr_peak_read.argtypes = [P, P, I64, I32, I32, P]
+        L.scqr_peak_read.restype = st
+        L.scqr_peak_write.argtypes = [P, P, I64, I32, I32]
+        L.scqr_peak_write.restype = st
+        L.scqr_peak_fp64.argtypes = [P, I32, I32, I32, P]
+        L.scqr_peak_fp64.restype = st
         L.scqr_gram.argtypes = [P, I64, I64, P, I64, ctypes.POINTER(_SpdOp), P, I64, P, SZ]
         L.scqr_gram.restype = st
         L.scqr_trsm.argtypes = [P, I64, I64, P, I64, P, I64, P, I64, P, SZ]
@@ -590,3 +598,30 @@ def profile_read(capacity: int = 1 << 16) -> list:
 def build_info() -> str:
     return lib().scqr_build_info().decode()
 
+
+def peak(kind: str, *tensors, variant: int = 0, grid: int = 0, iters: int = 0):
+    """Enqueue one device-ceiling kernel on the current stream (no part of a factorization):
+    kind "copy" (src, dst), "read" (src, sink), "write" (dst), "mfma" / "fma" (sink)."""
+    dev = tensors[0].device
+    S = _stream(dev)
+    L = lib()
+    if kind == "copy":
+        src, dst = tensors
+        st = L.scqr_peak_copy(S, src.data_ptr(), dst.data_ptr(), min(src.numel(), dst.numel()) * src.element_size(),
+                              variant, grid)
+    elif kind == "read":
+        src, sink = tensors
+        if sink.numel() < (grid or 2048) * 256:
+            raise ValueError("sink too small")
+        st = L.scqr_peak_read(S, src.data_ptr(), src.numel() * src.element_size(), variant, grid, sink.data_ptr())
+    elif kind == "write":
+        (dst,) = tensors
+        st = L.scqr_peak_write(S, dst.data_ptr(), dst.numel() * dst.element_size(), variant, grid)
+    elif kind in ("mfma", "fma"):
+        (sink,) = tensors
+        if sink.numel() < grid * 256:
+            raise ValueError("sink too small")
+        st = L.scqr_peak_fp64(S, 0 if kind == "mfma" else 1, iters, grid, sink.data_ptr())
+    else:
+        raise ValueError(kind)
+    _check(st, f"scqr_peak_{kind}")

@@ -382,7 +382,7 @@ void build_descriptors(const BatchArgs &a, const BatchPlan &bp, std::vector<unsi
             }
             I.t1 = t;
             if ((a.n[i] & 1) || (lx & 1) || (lq & 1) || (reinterpret_cast<uintptr_t>(a.X[i]) & 15) ||
-                (reinterpret_cast<uintptr_t>(a.Q[i]) & 15))
+                (reinterpret_cast<uintptr_t>(a.Q[i]) & 15) || lx > kBufMaxLd || lq > kBufMaxLd)
                 bc.vec = false;
         }
     }

@@ -131,30 +131,31 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
 #pragma unroll
     for (int u = 0; u < T; ++u) acc[u] = (d4){0.0, 0.0, 0.0, 0.0};
 
-    // X panel pn -> registers (pairs of doubles, coalesced); issued one panel ahead so that the
-    // loads of the next panel overlap the MFMA work of the current one.
+    // X panel pn -> registers (pairs of doubles, coalesced); issued one panel ahead, right after
+    // the current panel is staged in LDS, so that the loads of the next panel overlap the whole
+    // substitution, Q store and Gram of the current one.
+    // VEC: every pair a lane moves lies in column cl, rows rl + i * (128 / NP) of the panel;
+    // buffer accesses return zeros (loads) or are dropped (stores) past the end of the matrix,
+    // and padding columns (cl >= n) use an offset outside the resource.
     double2 pre[PP];
+    const int cl = 2 * (lane % (NP / 2)), rl = lane / (NP / 2);
+    constexpr int RSTEP = 128 / NP;
+    const uint32_t offx = cl < n ? (uint32_t)((rl * p.ldx + cl) * 8) : kBufOut;
+    const uint32_t dxs = (uint32_t)(RSTEP * p.ldx * 8);
     auto load_panel = [&](int64_t pnl) {
         const int64_t rb = pnl * PR;
+        if constexpr (VEC) {
+            const __amdgpu_buffer_rsrc_t rs = rows_rsrc(p.X, p.ldx, rb, p.m, n);
+#pragma unroll
+            for (int i = 0; i < PP; ++i) pre[i] = buf_load2(rs, offx + (uint32_t)i * dxs);
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < PP; ++i) {
             const int e2 = lane + 64 * i;
             const int r = e2 / (NP / 2), c = 2 * (e2 % (NP / 2));
             const int64_t row = rb + r;
-            if (VEC) {
-                // branch-free: load a valid pair (clamped address), zero it when out of range
-                const bool ok = row < p.m && c < n;
-                const int64_t rr = row < p.m ? row : p.m - 1;
-                const int cc = c < n ? c : 0;
-                double2 v;
-                if constexpr (BATCH) {
-                    const d2 g = *reinterpret_cast<gview<const d2>>(as_global(p.X) + rr * p.ldx + cc);
-                    v = make_double2(g.x, g.y);
-                } else {
-                    v = *reinterpret_cast<const double2 *>(p.X + rr * p.ldx + cc);
-                }
-                pre[i] = ok ? v : make_double2(0.0, 0.0);
-            } else {
+            {
                 double a = 0.0, b = 0.0;
                 if (row < p.m) {
                     const double *src = p.X + row * p.ldx + c;
@@ -178,6 +179,7 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
             *reinterpret_cast<double2 *>(P + r * S + c) = pre[i];
         }
         wave_sync();
+        if (nxt < npanels) load_panel(nxt);
         if (MODE >= 1) {
             // The opaque zero keeps the diagonal-block loads inside the panel loop (as scalar
             // loads of a 4 KB working set) instead of hoisting them into spilled registers.
@@ -294,6 +296,15 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
             }
             }
             // ---- Q panel -> HBM
+            if constexpr (VEC) {
+                const __amdgpu_buffer_rsrc_t rq = rows_rsrc(Qout, p.ldq, r0, p.m, n);
+                const uint32_t offq = cl < n ? (uint32_t)((rl * p.ldq + cl) * 8) : kBufOut;
+                const uint32_t dqs = (uint32_t)(RSTEP * p.ldq * 8);
+#pragma unroll
+                for (int i = 0; i < PP; ++i)
+                    buf_store2(rq, offq + (uint32_t)i * dqs,
+                               *reinterpret_cast<const double2 *>(P + (rl + RSTEP * i) * S + cl));
+            } else
 #pragma unroll
             for (int i = 0; i < PP; ++i) {
                 const int e2 = lane + 64 * i;
@@ -302,19 +313,13 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
                 if (row < p.m && c < n) {
                     const double2 v = *reinterpret_cast<const double2 *>(P + r * S + c);
                     double *dst = Qout + row * p.ldq + c;
-                    if (VEC) {
-                        if constexpr (BATCH)
-                            *reinterpret_cast<gview<d2>>(as_global(dst)) = (d2){v.x, v.y};
-                        else
-                            *reinterpret_cast<double2 *>(dst) = v;
-                    } else {
+                    {
                         dst[0] = v.x;
                         if (c + 1 < n) dst[1] = v.y;
                     }
                 }
             }
         }
-        if (nxt < npanels) load_panel(nxt);
         if (want_gram) {
             f4 acc32[F32 ? T : 1];
             if (F32) {
@@ -1601,8 +1606,9 @@ template <int NP>
 static hipError_t launch_small(hipStream_t s, const Problem &p, const Work &w, int mode, int pass,
                                bool f32, int final_gram)
 {
-    const bool aligned = (reinterpret_cast<uintptr_t>(p.X) & 15) == 0 && (p.ldx & 1) == 0 &&
-                         (mode == 0 || ((reinterpret_cast<uintptr_t>(p.Q) & 15) == 0 && (p.ldq & 1) == 0));
+    const bool aligned = (reinterpret_cast<uintptr_t>(p.X) & 15) == 0 && (p.ldx & 1) == 0 && p.ldx <= kBufMaxLd &&
+                         (mode == 0 || ((reinterpret_cast<uintptr_t>(p.Q) & 15) == 0 && (p.ldq & 1) == 0 &&
+                                        p.ldq <= kBufMaxLd));
     if (aligned && (p.n & 1) == 0)
         launch_small_v<NP, true>(s, p, w, mode, pass, f32, final_gram);
     else
@@ -1975,7 +1981,8 @@ hipError_t launch_solve_t(hipStream_t s, int np, int64_t m, int n, double *Y, in
     p.ldx = ldy;
     p.Q = Y;
     p.ldq = ldy;
-    const bool vec = (reinterpret_cast<uintptr_t>(Y) & 15) == 0 && (ldy & 1) == 0 && (n & 1) == 0;
+    const bool vec = (reinterpret_cast<uintptr_t>(Y) & 15) == 0 && (ldy & 1) == 0 && (n & 1) == 0 &&
+                     ldy <= kBufMaxLd;
     switch (np) {
     case 16: launch_solve_tile<16>(s, p, Rp, dinv, vec); break;
     case 32: launch_solve_tile<32>(s, p, Rp, dinv, vec); break;

@@ -162,6 +162,30 @@ __device__ __forceinline__ gview<T> as_global(T *p)
 {
     return (gview<T>)p;
 }
+// Raw buffer views of a row range of a row-major matrix: a 128-bit buffer access whose byte
+// offset (from the resource base) is at or beyond num_records reads zeros and writes nothing, so
+// rows past the end and padding columns need no per-lane clamping (offsets are given in 32 bits;
+// callers keep a panel within 2^31 bytes, see kBufMaxLd).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr uint32_t kBufOut = 0x80000000u;    // an offset beyond any resource built here
+constexpr int64_t kBufMaxLd = (int64_t)1 << 21;  // leading dimensions (doubles) the buffer path takes
+// Resource over the rows [r0, m) of an n-column matrix with leading dimension ld (doubles).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const double *base, int64_t ld, int64_t r0,
+                                                            int64_t m, int n)
+{
+    const int64_t rem = ((m - r0 - 1) * ld + n) * 8;
+    const int32_t nrec = rem > 0x7fffffff ? 0x7fffffff : (int32_t)rem;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(base + r0 * ld), (short)0, nrec, 0x00020000);
+}
+__device__ __forceinline__ double2 buf_load2(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_store2(__amdgpu_buffer_rsrc_t r, uint32_t off, double2 v)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
+}
+
 // A trivially copyable descriptor loaded as 8-byte words through a constant view.
 template <class T>
 __device__ __forceinline__ T load_cview(const T *p)

@@ -270,3 +270,18 @@ def test_noalloc_validation_without_device(L):
         for Bp in (None, ctypes.byref(spd)):
             assert L.scqr_workspace_bytes(1 << 30, n, Bp, None, ctypes.byref(sz)) == scqr.OK
             assert sz.value <= scqr.NOALLOC_SCRATCH_BYTES
+
+
+def test_autotune_candidates_and_cache_io(tmp_path, monkeypatch):
+    # host logic of the batched autotuner: candidate sets and the JSON cache round trip
+    from paper_1809_11085_amd import autotune
+    c64 = autotune.candidates(2, [(20000, 64), (50000, 60)])
+    assert (0, 32) in c64 and (0, 64) in c64 and all(r < 100000 for r, _ in c64)
+    c128 = autotune.candidates(3, [(3000, 128)])
+    assert all(p == 0 for _, p in c128) and all(r < 6000 for r, _ in c128)
+    monkeypatch.setenv("SCQR_AUTOTUNE_CACHE", str(tmp_path / "x" / "c.json"))
+    p = autotune.cache_path()
+    assert p == str(tmp_path / "x" / "c.json")
+    assert autotune._load_cache(p) == {}
+    autotune._store_cache(p, {"k": {"rows_per_task": 2048, "panel_rows": 32}})
+    assert autotune._load_cache(p)["k"]["rows_per_task"] == 2048

@@ -258,3 +258,79 @@ def test_batched_instance_beyond_2_32_elements(scqr, my, n, inst):
         Rk = Rs[k].cpu().numpy()
         assert np.linalg.norm(Rk - rs.R) <= 1e-10 * np.linalg.norm(rs.R), k
         assert accuracy.orthogonality(Qs[k].cpu().numpy())[0] <= 1e-13, k
+
+
+def _metrics64(X, Q, R):
+    # binary64 BLAS products: their rounding (about sqrt(m) u) stays far below the 1e-13 bar
+    n = Q.shape[1]
+    om = float(np.max(np.abs(np.linalg.eigvalsh(Q.T @ Q - np.eye(n)))))
+    return om, float(np.linalg.norm(X - Q @ R) / np.linalg.norm(X))
+
+
+@pytest.mark.slow
+def test_c4_full_batch_all_instances(scqr):
+    """The full 512-instance batch (m_i in [1e4, 2e5], n_i in {16, 32, 64, 128}, kappa_i in
+    [1e4, 1e15]) in one batched call, all-FP64 and FP32-first: every instance succeeds with
+    ||Q^T Q - I||_2 <= 1e-13 and ||X - QR||_F / ||X||_F <= 1e-13, and the FP32-first R agrees
+    with the FP64 R to within kappa_i * 1e-14 (both are backward stable factors of X_i)."""
+    spec = synth.batch_spec(512)
+    print(f"c4 full batch: generating {len(spec)} instances", flush=True)
+    Xh = [synth.randsvd(s.m, s.n, s.kappa, seed=s.seed) for s in spec]
+    Xs = [torch.from_numpy(X).cuda() for X in Xh]
+    shapes = [(s.m, s.n) for s in spec]
+    Rf = None
+    for prec in ("fp64", "fp32_first"):
+        print(f"c4 full batch: {prec}", flush=True)
+        bp = scqr.BatchedPlan(shapes, "cuda", precision=prec)
+        bp.run(Xs)
+        infos = bp.read_infos()
+        Rc = []
+        for i, s in enumerate(spec):
+            assert infos[i].status == scqr.OK, (prec, i, s, infos[i])
+            Qh, Rh = host(bp.Qs[i]), host(bp.Rs[i])
+            om, rho = _metrics64(Xh[i], Qh, Rh)
+            assert om <= 1e-13 and rho <= 1e-13, (prec, i, s, om, rho)
+            assert np.all(np.diag(Rh) > 0) and np.all(np.tril(Rh, -1) == 0), (prec, i)
+            Rc.append(Rh)
+        if Rf is None:
+            Rf = Rc
+        else:
+            for i, s in enumerate(spec):
+                d = np.linalg.norm(Rc[i] - Rf[i]) / np.linalg.norm(Rf[i])
+                assert d <= max(s.kappa, 1e2) * 1e-14, (i, s, d)
+        del bp
+        torch.cuda.empty_cache()
+
+
+def test_batched_autotune_cached_and_correct(scqr, batch_inputs, tmp_path, monkeypatch):
+    """The autotuner times candidate tunings per width class, caches the winner, answers from the
+    cache the second time, and a plan built with tuning="auto" factors the batch correctly."""
+    import json
+    import os
+
+    from paper_1809_11085_amd import autotune
+
+    cache = tmp_path / "autotune.json"
+    monkeypatch.setenv("SCQR_AUTOTUNE_CACHE", str(cache))
+    sel = [0, 3, 5, 8, 9, 13]
+    shapes = [BATCH[i][:2] for i in sel]
+    t = autotune.tune(shapes, "cuda", reps=1)
+    assert cache.exists()
+    stored = json.loads(cache.read_text())
+    classes = sorted({scqr.class_of(n) for _, n in shapes})
+    assert sorted(v["class"] for v in stored.values()) == classes
+    for c in classes:
+        sh = [s for s in shapes if scqr.class_of(s[1]) == c]
+        assert (t["rows_per_task"][c], t["panel_rows"][c]) in autotune.candidates(c, sh)
+    mtime = os.path.getmtime(cache)
+    assert autotune.tune(shapes, "cuda", reps=1) == t
+    assert os.path.getmtime(cache) == mtime
+    Xs = [torch.from_numpy(batch_inputs[i]).cuda() for i in sel]
+    plan = scqr.BatchedPlan(shapes, "cuda", Xs=Xs, tuning="auto")
+    Qs, Rs = plan.run(Xs)
+    infos = plan.read_infos()
+    for k, i in enumerate(sel):
+        assert infos[k].status == scqr.OK
+        Qh, Rh = host(Qs[k]), host(Rs[k])
+        assert accuracy.orthogonality(Qh)[0] <= 1e-13
+        assert accuracy.residual(batch_inputs[i], Qh, Rh) <= 1e-13
