@@ -87,11 +87,20 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
     constexpr int NT = NP / 16;
     constexpr int T = NT * (NT + 1) / 2;
     constexpr int NOFF = NT * (NT - 1) / 2;
-    constexpr int S = NP + 2;  // LDS row stride (doubles): 2*S = 4 mod 32 dwords
+    // LDS row stride (doubles): 2 S = 4 (mod 64) dwords, so that one row per lane (per-lane
+    // substitution, 16-byte reads) and 16 rows by 4 consecutive columns (MFMA A operands) are
+    // free of bank conflicts on the 64 banks.  Where a half-wave reads two rows across 16
+    // consecutive columns (MFMA result tiles and Gram operands), the rows are chosen 8 apart
+    // (2 S * 8 = 32 mod 64), which puts them on opposite halves of the banks:
+    //   MFMA row index i = lk + 4 r of a 16-row group <-> panel row rowperm(i) = 8 (i & 1) +
+    //   4 ((i >> 1) & 1) + (i >> 2);   Gram k-step s, lane row lk <-> panel row (s & 7) + 8 lk +
+    //   32 (s >> 3).  Every row is still solved and summed exactly once.
+    constexpr int S = NP + 2;
     constexpr int PANEL = PR * S;
     constexpr int LDSZ = (WAVES * PANEL > T * 256) ? WAVES * PANEL : T * 256;
     constexpr int PP = PR * NP / 2 / 64;  // double pairs per lane per panel
     static_assert((PR * NP / 2) % 64 == 0, "panel must split evenly over a wave");
+    static_assert(PR % 32 == 0, "Gram row mapping covers 32-row blocks");
     static_assert(!F32 || PR == f32_chain_rows(NP), "a binary32 chain is one panel");
     constexpr int BL = (MODE >= 1 && NOFF > 0) ? NOFF * 4 * 64 : 1;
     __shared__ __attribute__((aligned(16))) double lds[LDSZ];
@@ -108,6 +117,8 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
     const int n = p.n;
     double *P = lds + wv * PANEL;
     const int li = lane & 15, lk = lane >> 4;
+    const int pli = 8 * (li & 1) + 4 * ((li >> 1) & 1) + (li >> 2);  // rowperm(li)
+    const int plk = 8 * (lk & 1) + 4 * (lk >> 1);                    // rowperm(lk + 4 r) - r
 
     // -R~_KJ (K < J) in the B-operand layout, one 64-entry vector per (block pair, k-step):
     // entry l holds -r[16K + 4s + l/16][16J + l%16].
@@ -193,11 +204,11 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
                     if (JB < NT - 1) {
 #pragma unroll
                         for (int g = 0; g < PR / 16; ++g) {
-                            double *blk = P + (16 * g + lk) * S + 16 * JB + li;
+                            double *blk = P + (16 * g + plk) * S + 16 * JB + li;
                             d4 d;
 #pragma unroll
-                            for (int r = 0; r < 4; ++r) d[r] = blk[4 * r * S];
-                            const double *arow = P + (16 * g + li) * S + lk;
+                            for (int r = 0; r < 4; ++r) d[r] = blk[r * S];
+                            const double *arow = P + (16 * g + pli) * S + lk;
 #pragma unroll
                             for (int J2 = JB + 1; J2 < NT; ++J2) {
                                 const int pi = J2 * (J2 - 1) / 2 + JB;
@@ -207,7 +218,7 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
                                                                              bl[(pi * 4 + s4) * 64 + lane], d, 0, 0, 0);
                             }
 #pragma unroll
-                            for (int r = 0; r < 4; ++r) blk[4 * r * S] = d[r];
+                            for (int r = 0; r < 4; ++r) blk[r * S] = d[r];
                         }
                         wave_sync();
                     }
@@ -242,11 +253,11 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
                 if (J > 0) {
 #pragma unroll
                     for (int g = 0; g < PR / 16; ++g) {
-                        double *blk = P + (16 * g + lk) * S + 16 * J + li;
+                        double *blk = P + (16 * g + plk) * S + 16 * J + li;
                         d4 d;
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) d[r] = blk[4 * r * S];
-                        const double *arow = P + (16 * g + li) * S + lk;
+                        for (int r = 0; r < 4; ++r) d[r] = blk[r * S];
+                        const double *arow = P + (16 * g + pli) * S + lk;
                         int pi = pi0;
 #pragma unroll
                         for (int K = 0; K < J; ++K, ++pi)
@@ -255,7 +266,7 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
                                 d = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * K + 4 * s4],
                                                                          bl[(pi * 4 + s4) * 64 + lane], d, 0, 0, 0);
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) blk[4 * r * S] = d[r];
+                        for (int r = 0; r < 4; ++r) blk[r * S] = d[r];
                     }
                     pi0 += J;
                     wave_sync();
@@ -328,7 +339,7 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
             }
 #pragma unroll
             for (int s = 0; s < PR / 4; ++s) {
-                const double *src = P + (4 * s + lk) * S + li;
+                const double *src = P + ((s & 7) + 8 * lk + 32 * (s >> 3)) * S + li;
                 if (F32) {
                     float op[NT];
 #pragma unroll
