@@ -38,7 +38,7 @@ _SRC = os.path.join(_HERE, "scqr_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 FIXED3, ADAPTIVE, CHOLQR2, ITERATED = 0, 1, 2, 3
-SHIFT_PAPER, SHIFT_FRO, SHIFT_SMALL, SHIFT_CUSTOM = 0, 1, 2, 3
+SHIFT_PAPER, SHIFT_FRO, SHIFT_SMALL, SHIFT_CUSTOM, SHIFT_DEPTH = 0, 1, 2, 3, 4
 OK, INVALID, BREAKDOWN, NOT_CONVERGED, NONFINITE = 0, 1, 5, 6, 7
 U = 2.0 ** -53
 U32 = 2.0 ** -24
@@ -61,7 +61,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("shift_mode", ctypes.c_int32),
                 ("max_passes", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("f32_chain", ctypes.c_int32), ("force_breakdown_pass", ctypes.c_int32),
-                ("zero_shift", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("zero_shift", ctypes.c_int32), ("gram_chunk", ctypes.c_int32),
                 ("custom_alpha", ctypes.c_double), ("bnorm", ctypes.c_double)]
 
 
@@ -85,6 +85,9 @@ def lib():
             "orc_gram_tridiag": (None, [I64, I64, P, I64, P, P, P]),
             "orc_gram_dense": (None, [I64, I64, P, I64, P, P]),
             "orc_gram_f32": (None, [I64, I64, P, I64, I64, P]),
+            "orc_gram_chunked": (None, [I64, I64, P, I64, I64, P]),
+            "orc_gram_depth": (I64, [I64, I64]),
+            "orc_shift_depth": (D, [I64, I64, D]),
             "orc_sym_eig": (None, [I64, P, P]),
             "orc_lambda_max": (D, [I64, P]),
             "orc_chol_upper": (ctypes.c_int, [I64, P, D, P]),
@@ -153,6 +156,25 @@ def gram_f32(X, chain: int):
     A = np.empty((n, n))
     lib().orc_gram_f32(m, n, _p(X), n, int(chain), _p(A))
     return A
+
+
+def gram_chunked(X, chunk: int):
+    """A = X^T X summed over consecutive chunks of `chunk` rows, then over the chunks."""
+    X = _c(X)
+    m, n = X.shape
+    A = np.empty((n, n))
+    lib().orc_gram_chunked(m, n, _p(X), n, int(chunk), _p(A))
+    return A
+
+
+def gram_depth(m: int, chunk: int) -> int:
+    """Summation depth of gram_chunked: chunk + ceil(m / chunk) (m when chunk >= m)."""
+    return int(lib().orc_gram_depth(int(m), int(chunk)))
+
+
+def shift_depth(depth: int, n: int, norm2sq: float) -> float:
+    """s = 11 (d n + n (n+1)) u ||X||_2^2 for a Gram of summation depth d."""
+    return lib().orc_shift_depth(int(depth), int(n), float(norm2sq))
 
 
 def sym_eig(A):
@@ -233,14 +255,16 @@ class Result:
 
 def scqr(X, schedule=FIXED3, shift_mode=SHIFT_PAPER, max_passes=6, B=None, tridiag=None,
          precision=0, f32_chain=None, force_breakdown_pass=0, zero_shift=False, custom_alpha=0.0,
-         bnorm=0.0, history=False) -> Result:
-    """Run the oracle's driver; ``tridiag=(diag, off)`` or dense ``B`` select the oblique form."""
+         bnorm=0.0, history=False, gram_chunk=0) -> Result:
+    """Run the oracle's driver; ``tridiag=(diag, off)`` or dense ``B`` select the oblique form.
+    ``shift_mode=SHIFT_DEPTH`` sums every Gram in chunks of ``gram_chunk`` rows and shifts with
+    the depth of that summation (Euclidean inner product only)."""
     X = _c(X)
     m, n = X.shape
     if f32_chain is None:
         f32_chain = f32_chain_rows(n)
     o = _Opts(schedule, shift_mode, max_passes, precision, f32_chain, force_breakdown_pass,
-              int(bool(zero_shift)), 0, custom_alpha, bnorm)
+              int(bool(zero_shift)), int(gram_chunk), custom_alpha, bnorm)
     info = _Info()
     Q = np.empty((m, n))
     R = np.empty((n, n))

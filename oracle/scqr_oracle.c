@@ -33,7 +33,7 @@
 
 enum { ORC_OK = 0, ORC_BREAKDOWN = 5, ORC_NOT_CONVERGED = 6, ORC_NONFINITE = 7, ORC_INVALID = 1 };
 enum { ORC_FIXED3 = 0, ORC_ADAPTIVE = 1, ORC_CHOLQR2 = 2, ORC_ITERATED = 3 };
-enum { ORC_SHIFT_PAPER = 0, ORC_SHIFT_FRO = 1, ORC_SHIFT_SMALL = 2, ORC_SHIFT_CUSTOM = 3 };
+enum { ORC_SHIFT_PAPER = 0, ORC_SHIFT_FRO = 1, ORC_SHIFT_SMALL = 2, ORC_SHIFT_CUSTOM = 3, ORC_SHIFT_DEPTH = 4 };
 enum { ORC_B_NONE = 0, ORC_B_TRIDIAG = 1, ORC_B_DENSE = 2 };
 
 /* ------------------------------------------------------------------------------------------
@@ -187,6 +187,45 @@ void orc_gram_f32(int64_t m, int64_t n, const double *X, int64_t ldx, int64_t ch
         free(part);
         free(tot);
     }
+}
+
+/* A = X^T X with the rows summed in consecutive chunks of `chunk` rows: each chunk's products
+ * are added in row order starting from zero, and the chunk sums are added in chunk order.  Every
+ * product then takes part in at most orc_gram_depth(m, chunk) roundings (its own, the additions
+ * inside its chunk, the additions of the chunk sums), which is the depth that replaces m in the
+ * gamma_m bound of the Gram error (Section 3.1.1) for this summation order. */
+void orc_gram_chunked(int64_t m, int64_t n, const double *X, int64_t ldx, int64_t chunk, double *A)
+{
+    if (chunk < 1) chunk = 1;
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t i = 0; i < n; ++i) {
+        double *tot = (double *)calloc((size_t)n, sizeof(double));
+        double *part = (double *)calloc((size_t)n, sizeof(double));
+        for (int64_t k0 = 0; k0 < m; k0 += chunk) {
+            const int64_t k1 = (k0 + chunk < m) ? k0 + chunk : m;
+            for (int64_t j = i; j < n; ++j) part[j] = 0.0;
+            for (int64_t k = k0; k < k1; ++k) {
+                const double xi = X[k * ldx + i];
+                for (int64_t j = i; j < n; ++j) part[j] = part[j] + xi * X[k * ldx + j];
+            }
+            for (int64_t j = i; j < n; ++j) tot[j] = tot[j] + part[j];
+        }
+        for (int64_t j = i; j < n; ++j) {
+            A[i * n + j] = tot[j];
+            A[j * n + i] = tot[j];
+        }
+        free(part);
+        free(tot);
+    }
+}
+
+/* Summation depth of orc_gram_chunked: chunk + ceil(m / chunk) (m itself bounds the depth of
+ * the row-order recursive sum of orc_gram). */
+int64_t orc_gram_depth(int64_t m, int64_t chunk)
+{
+    if (chunk < 1) chunk = 1;
+    if (chunk >= m) return m;
+    return chunk + (m + chunk - 1) / chunk;
 }
 
 /* ------------------------------------------------------------------------------------------
@@ -353,6 +392,16 @@ double orc_shift(int64_t m, int64_t n, double norm2sq, double bnorm, int oblique
     return c * norm2sq * bnorm;
 }
 
+/* Summation-depth shift (the shift-policy question the paper leaves open in its remark after
+ * Table 3 and its conclusion): the derivation of equation (eq:finds2) with gamma_m, the bound of a
+ * Gram summed over m rows in sequence, replaced by gamma_d for a Gram whose sums have depth d:
+ *   s = 11 (d n + n (n+1)) u ||X||_2^2;  d = m gives equation (eq:finds2). */
+double orc_shift_depth(int64_t depth, int64_t n, double norm2sq)
+{
+    const double dd = (double)depth, dn = (double)n;
+    return 11.0 * (dd * dn + dn * (dn + 1.0)) * ORC_U * norm2sq;
+}
+
 /* Shift of an FP32-first pass (not in the paper): the Gram error of a binary32 chain of
  * `chain` rows plus the rounding of X to binary32 is bounded like gamma_{chain+2} in u32,
  * and the Cholesky itself runs in binary64:
@@ -384,7 +433,7 @@ typedef struct {
     int32_t f32_chain;           /* rows per binary32 chain for FP32-first */
     int32_t force_breakdown_pass; /* debug: the Cholesky of this pass (1-based) reports breakdown */
     int32_t zero_shift;          /* debug: every shift is 0 */
-    int32_t pad;
+    int32_t gram_chunk;          /* ORC_SHIFT_DEPTH: rows per chunk of every Gram */
     double custom_alpha;
     double bnorm;                /* >0: ||B||_2 bound given by caller */
 } orc_opts;
@@ -420,7 +469,9 @@ int orc_scqr(int64_t m, int64_t n, const double *X, int64_t ldx, int32_t bkind,
              orc_info *info, double *gram_hist, double *rt_hist)
 {
     memset(info, 0, sizeof(*info));
-    if (m < n || n < 1 || ldx < n || opt->max_passes < 1 || opt->max_passes > 16) {
+    const int depth_mode = opt->shift_mode == ORC_SHIFT_DEPTH;
+    if (m < n || n < 1 || ldx < n || opt->max_passes < 1 || opt->max_passes > 16 ||
+        (depth_mode && (bkind != ORC_B_NONE || opt->gram_chunk < 1))) {
         info->status = ORC_INVALID;
         return ORC_INVALID;
     }
@@ -469,6 +520,8 @@ int orc_scqr(int64_t m, int64_t n, const double *X, int64_t ldx, int32_t bkind,
             orc_gram_tridiag(m, n, Q, n, b0, b1, A);
         else if (bkind == ORC_B_DENSE)
             orc_gram_dense(m, n, Q, n, b0, A);
+        else if (depth_mode)
+            orc_gram_chunked(m, n, Q, n, opt->gram_chunk, A);
         else
             orc_gram(m, n, Q, n, A);
         if (!all_finite(nn, A)) {
@@ -496,6 +549,9 @@ int orc_scqr(int64_t m, int64_t n, const double *X, int64_t ldx, int32_t bkind,
         }
         const double bfac = (first && oblique) ? bnorm : 1.0;
         info->norm2sq[p - 1] = norm2sq;
+        const double s_pass = depth_mode ? orc_shift_depth(orc_gram_depth(m, opt->gram_chunk), n, norm2sq)
+                                         : orc_shift(m, n, norm2sq, bfac, oblique, opt->shift_mode,
+                                                     opt->custom_alpha);
 
         const int forced = (opt->force_breakdown_pass == p);
         const int shift_first = first && (opt->schedule == ORC_FIXED3 || opt->schedule == ORC_ADAPTIVE);
@@ -519,7 +575,7 @@ int orc_scqr(int64_t m, int64_t n, const double *X, int64_t ldx, int32_t bkind,
                     bd = orc_chol_upper(n, A, s, Rt);
                 }
             } else {
-                s = orc_shift(m, n, norm2sq, bfac, oblique, opt->shift_mode, opt->custom_alpha);
+                s = s_pass;
                 if (opt->zero_shift) s = 0.0;
                 bd = forced ? 1 : orc_chol_upper(n, A, s, Rt);
             }
@@ -537,8 +593,7 @@ int orc_scqr(int64_t m, int64_t n, const double *X, int64_t ldx, int32_t bkind,
             if (bd) {
                 info->breakdown_mask |= 1 << (p - 1);
                 if (opt->schedule == ORC_ADAPTIVE || opt->schedule == ORC_ITERATED) {
-                    s = orc_shift(m, n, norm2sq, bfac, oblique, opt->shift_mode,
-                                  opt->custom_alpha);
+                    s = s_pass;
                     if (opt->zero_shift) s = 0.0;
                     shifted = 1;
                     info->shift[p - 1] = s;
