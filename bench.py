@@ -60,9 +60,9 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str, workload: str, launches_bytes: float):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary of this kernel and
-    workload, scaled by the copy-kernel calibration, or None when missing or stale."""
+def committed_profile(kernel: str, workload: str):
+    """The committed rocprofv3 summary of this kernel and workload (profiles/*_counters.json),
+    or None when missing or taken from other kernel sources (its source hash differs)."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.json")
     if not os.path.exists(path):
         return None
@@ -70,7 +70,14 @@ def traffic_from_profiles(kernel: str, workload: str, launches_bytes: float):
         c = json.load(fh)
     if c.get("source_hash") != source_hash():
         return None
-    return c.get("hbm_bytes_per_launch")
+    return c
+
+
+def traffic_from_profiles(kernel: str, workload: str, launches_bytes: float):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary of this kernel and
+    workload, scaled by the copy-kernel calibration, or None when missing or stale."""
+    c = committed_profile(kernel, workload)
+    return None if c is None else c.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(X, passes_gpu, schedule, min_seconds=10.0, max_runs=15):
@@ -188,6 +195,45 @@ def extra_c2b(scqr, synth):
                       "TFLOP/s": round(flops_of(m, n, info.passes) / ms / 1e9, 3)}
         del plan
     out["speedup_cholqr2_vs_scholqr3"] = round(out["fixed3"]["ms"] / out["cholqr2"]["ms"], 3)
+    del X
+    torch.cuda.empty_cache()
+    return out
+
+
+def extra_f2(scqr, synth):
+    """c2 (2^22 x 64, kappa = 1e15) with the summation-depth shift: time, passes, the depth the
+    library reports and the accuracy, beside the paper's shift, and the oracle's pass count in the
+    same mode (its Gram summed in chunks of 2048 rows) beside the oracle's paper-shift count."""
+    import numpy as np
+    import torch
+
+    import accuracy
+    import oracle
+
+    m, n = 1 << 22, 64
+    Xh = synth.randsvd(m, n, 1e15, seed=synth.seed_for(1))
+    X = torch.from_numpy(Xh).cuda()
+    out = {}
+    for shift in ("depth", "paper"):
+        plan = scqr.Plan(m, n, "cuda", schedule="adaptive", shift=shift)
+        ms = _time_ms(lambda: plan.run(X), reps=5)
+        info = plan.read_info()
+        out[shift] = {"ms": round(ms, 4), "passes": info.passes, "status": scqr.status_string(info.status),
+                      "shifts": info.shift, "gram_depth": info.gram_depth,
+                      "TFLOP/s": round(flops_of(m, n, info.passes) / ms / 1e9, 3)}
+        if shift == "depth":
+            Qh, Rh = plan.Q.cpu().numpy(), plan.R.cpu().numpy()
+            om, _ = accuracy.orthogonality(Qh)
+            out[shift]["orthogonality_2"] = om
+            out[shift]["residual"] = accuracy.residual(Xh, Qh, Rh)
+        del plan
+    chunk = 2048
+    rd = oracle.scqr(Xh, schedule=oracle.ADAPTIVE, shift_mode=oracle.SHIFT_DEPTH, gram_chunk=chunk)
+    rp = oracle.scqr(Xh, schedule=oracle.ADAPTIVE)
+    out["oracle"] = {"depth_mode": {"passes": rd.passes, "status": rd.status, "gram_chunk": chunk,
+                                    "gram_depth": oracle.gram_depth(m, chunk), "shifts": rd.shifts},
+                     "paper_shift": {"passes": rp.passes, "status": rp.status}}
+    out["speedup_depth_vs_paper_shift"] = round(out["paper"]["ms"] / out["depth"]["ms"], 3)
     del X
     torch.cuda.empty_cache()
     return out
@@ -471,7 +517,7 @@ def main():
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="write profiles/<kernel>_<workload>.md and _counters.json from the rocprofv3 "
                          "outputs under DIR (trace/, fetch/, write/, cfetch/, cwrite/)")
-    ap.add_argument("--extras", default="c2b,c3,c4,c5")
+    ap.add_argument("--extras", default="c2b,f2,c3,c4,c5")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -561,7 +607,14 @@ def main():
     traffic = traffic_from_profiles(dom, args.workload, unit_bytes)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "bytes_per_launch": unit_bytes, "avg_launch_ms": round(avg, 5)}
+                "bytes_per_launch": unit_bytes, "avg_launch_ms": round(avg, 5),
+                "timing": "HIP events on the launch stream around every launch of this run (primary)"}
+    prof = committed_profile(dom, args.workload)
+    if prof is not None:
+        # the same kernel's average from the committed rocprofv3 kernel trace (same sources)
+        a2 = prof["avg_active_ms_rocprof"]
+        roofline["avg_launch_ms_rocprof"] = round(a2, 5)
+        roofline["frac_rocprof"] = round(unit_bytes / (a2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     # whole-path roofline: bytes (8 + 16 p) m n at 8 TB/s vs flops at 78.6 TFLOP/s; secondary:
     # the minimum-traffic variant that recomputes every Q from X (X read by each pass's Gram and
     # by the final substitution, Q written once: 8 (p + 2) m n bytes, 40 m n at p = 3)
@@ -606,7 +659,7 @@ def main():
         result["cpu_baseline"]["value"] = round(cb["value"], 5)
         log(f"[bench] cpu baseline: {cb['value'] * 1e3:.2f} GFLOP/s on {cb['cores']} threads")
     if args.workload == "c2" and not args.no_extras:
-        fns = {"c2b": extra_c2b, "c3": extra_c3, "c4": extra_c4, "c5": extra_c5}
+        fns = {"c2b": extra_c2b, "f2": extra_f2, "c3": extra_c3, "c4": extra_c4, "c5": extra_c5}
         extras, speed = {}, {}
         for name in [x for x in args.extras.split(",") if x]:
             t = time.perf_counter()
@@ -616,7 +669,7 @@ def main():
                 extras[name] = {"error": f"{type(exc).__name__}: {exc}"}
             log(f"[bench] extra {name}: {extras[name]} ({time.perf_counter() - t:.1f} s)")
         for name, key in (("c4", "speedup_batched_vs_loop"), ("c4", "speedup_mixed_vs_fp64_batched"),
-                          ("c2b", "speedup_cholqr2_vs_scholqr3")):
+                          ("c2b", "speedup_cholqr2_vs_scholqr3"), ("f2", "speedup_depth_vs_paper_shift")):
             if key in extras.get(name, {}):
                 speed[f"{name}_{key[8:]}"] = extras[name][key]
         result["speedups"] = speed

@@ -65,15 +65,23 @@ enum {
     SCQR_SHIFT_PAPER = 0,  /* (eq:finds2)/(eq:finds2B) with ||.||_2^2 from a power iteration  */
     SCQR_SHIFT_FRO = 1,    /* the same with ||X||_F^2 in place of ||X||_2^2 (Section 4.1)    */
     SCQR_SHIFT_SMALL = 2,  /* s = u ||X||_2^2 (||B||_2): remark after Table 3; no guarantee   */
-    SCQR_SHIFT_CUSTOM = 3  /* s = custom_alpha ||X||_2^2 (||B||_2)                            */
+    SCQR_SHIFT_CUSTOM = 3, /* s = custom_alpha ||X||_2^2 (||B||_2)                            */
+    SCQR_SHIFT_DEPTH = 4   /* s = 11 (d n + n (n+1)) u ||X||_2^2: (eq:finds2) with the gamma_m
+                              bound of the Gram (Section 3.1.1) replaced by gamma_d, d a bound
+                              on the summation depth of the library's Gram for this launch
+                              (rows one workgroup accumulates plus the fixed-order reductions;
+                              reported in scqr_info.gram_depth).  Not in the paper, which leaves
+                              a smaller safe shift open (remark after Table 3, Section 8).
+                              Euclidean inner product only. */
 };
 
 /* Arithmetic of the first (preconditioning) pass. */
 enum {
     SCQR_PREC_FP64 = 0,
     SCQR_PREC_FP32_FIRST = 1 /* first Gram in binary32 MFMA (binary64 reduction) with shift
-                                s32 = 11 ((k+2) n u32 + n (n+1) u) ||X||_2^2, k = 64 rows per
-                                binary32 chain, u32 = 2^-24; if s32 > ||X||_2^2 / 100 or its
+                                s32 = 11 ((k+2) n u32 + n (n+1) u) ||X||_2^2, k the rows of one
+                                binary32 chain (32 for n <= 64, 64 for n <= 128, 16 beyond),
+                                u32 = 2^-24; if s32 > ||X||_2^2 / 100 or its
                                 Cholesky breaks down, that pass is redone in binary64.  Not in
                                 the paper; Euclidean inner product only. */
 };
@@ -107,6 +115,8 @@ typedef struct {
     double gram_dev[SCQR_MAX_PASSES]; /* ||A_p - I||_F of the input Gram of pass p            */
     double omega_fro;       /* final_gram: ||Q^T Q - I||_F (or Q^T B Q) from the device Gram  */
     double bnorm;           /* ||B||_2 bound used (1 for B = I)                               */
+    double gram_depth;      /* bound on the summation depth of the binary64 Grams (the d of
+                               SCQR_SHIFT_DEPTH; reported for every shift mode)                */
 } scqr_info;
 
 /* Optional SPD operator B of the oblique inner product (Section 5).  NULL or kind NONE means

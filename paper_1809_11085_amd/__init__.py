@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(_HERE, "libscqr.so")
 
 OK, E_INVALID, E_WORKSPACE, E_UNSUPPORTED, E_HIP, E_BREAKDOWN, E_NOT_CONVERGED, E_NONFINITE = range(8)
 SCHEDULES = {"fixed3": 0, "adaptive": 1, "cholqr2": 2, "iterated": 3}
-SHIFTS = {"paper": 0, "fro": 1, "small": 2, "custom": 3}
+SHIFTS = {"paper": 0, "fro": 1, "small": 2, "custom": 3, "depth": 4}
 PRECISIONS = {"fp64": 0, "fp32_first": 1}
 MAX_PASSES = 16
 
@@ -75,7 +75,7 @@ class _Info(ctypes.Structure):
                 ("fell_back_fp64", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("shift", ctypes.c_double * MAX_PASSES), ("norm2sq", ctypes.c_double * MAX_PASSES),
                 ("gram_dev", ctypes.c_double * MAX_PASSES), ("omega_fro", ctypes.c_double),
-                ("bnorm", ctypes.c_double)]
+                ("bnorm", ctypes.c_double), ("gram_depth", ctypes.c_double)]
 
 
 class _SpdOp(ctypes.Structure):
@@ -227,6 +227,7 @@ class Info:
     gram_dev: list
     omega_fro: float
     bnorm: float
+    gram_depth: float = 0.0
 
     @property
     def ok(self) -> bool:
@@ -239,7 +240,8 @@ def decode_info(buf: torch.Tensor) -> Info:
     c = _Info.from_buffer_copy(raw[:INFO_BYTES])
     k = max(c.passes + (1 if c.status == E_BREAKDOWN else 0), 1)
     return Info(c.status, c.passes, c.shifted_mask, c.breakdown_mask, c.fell_back_fp64,
-                list(c.shift[:k]), list(c.norm2sq[:k]), list(c.gram_dev[:k]), c.omega_fro, c.bnorm)
+                list(c.shift[:k]), list(c.norm2sq[:k]), list(c.gram_dev[:k]), c.omega_fro, c.bnorm,
+                c.gram_depth)
 
 
 class Plan:

@@ -66,10 +66,22 @@ size_t mat_bytes(int64_t rows, int64_t cols, int64_t ld)
     return sizeof(double) * (size_t)((rows - 1) * ld + cols);
 }
 
+// Bound on the summation depth of the binary64 Grams (the d of SCQR_SHIFT_DEPTH): the rows
+// one accumulator chain takes (at most the rows of one workgroup: ceil(m / nwg) plus a partial
+// panel round, 256 rows), the four products of one MFMA step, the fixed-order sum over the
+// waves of a workgroup (at most 16) and the two reduction levels (32 partials, then nlvl2).
+double gram_depth_single(int64_t m, int nwg, int nlvl2)
+{
+    return (double)((m + nwg - 1) / nwg + 256 + 4 + 16 + 32 + nlvl2);
+}
+// Batched: a task of task_rows rows is one workgroup's chain; the instance's ntask partials
+// are summed in one sequence.
+double gram_depth_batched(int64_t task_rows, int ntask) { return (double)(task_rows + 256 + 4 + 16 + ntask); }
+
 scqr_status check_opts(const scqr_opts *o)
 {
     if (o->schedule < 0 || o->schedule > 3) return SCQR_E_INVALID;
-    if (o->shift_mode < 0 || o->shift_mode > 3) return SCQR_E_INVALID;
+    if (o->shift_mode < 0 || o->shift_mode > 4) return SCQR_E_INVALID;
     if (o->precision < 0 || o->precision > 1) return SCQR_E_INVALID;
     if (o->max_passes < 1 || o->max_passes > SCQR_MAX_PASSES) return SCQR_E_INVALID;
     if (o->shift_mode == SCQR_SHIFT_CUSTOM && !(o->custom_alpha >= 0.0)) return SCQR_E_INVALID;
@@ -353,6 +365,7 @@ void build_descriptors(const BatchArgs &a, const BatchPlan &bp, std::vector<unsi
             I.p.R = a.R[i];
             I.p.ldr = lr;
             I.p.zero = 0;
+            I.p.gram_depth = gram_depth_batched(bp.task_rows[i], bp.ntask[i]);
             char *blk = base + bp.inst_off[i];
             size_t o2 = 0;
             I.w.ctl = reinterpret_cast<Ctl *>(blk + o2);
@@ -566,6 +579,7 @@ scqr_status qr_enqueue(void *stream, int64_t m, int64_t n, const double *X, int6
     if (st != SCQR_OK) return st;
     const bool obl = is_oblique(B);
     if (obl && o.precision == SCQR_PREC_FP32_FIRST) return SCQR_E_UNSUPPORTED;
+    if (obl && o.shift_mode == SCQR_SHIFT_DEPTH) return SCQR_E_UNSUPPORTED;
     // aliasing: Q may equal X exactly; R must not overlap X, Q or the workspace
     const size_t xb = mat_bytes(m, n, ldx), qb = mat_bytes(m, n, ldq), rb = mat_bytes(n, n, ldr);
     if (Q != X && ranges_overlap(X, xb, Q, qb)) return SCQR_E_INVALID;
@@ -591,6 +605,7 @@ scqr_status qr_enqueue(void *stream, int64_t m, int64_t n, const double *X, int6
     p.ldr = ldr;
     p.bdiag = obl ? B->diag : nullptr;
     p.boff = obl ? B->off : nullptr;
+    p.gram_depth = gram_depth_single(m, L.nwg, L.nlvl2);
     SchedParams sp;
     sp.schedule = o.schedule;
     sp.shift_mode = o.shift_mode;
@@ -627,7 +642,7 @@ scqr_status qr_enqueue(void *stream, int64_t m, int64_t n, const double *X, int6
             pp.ldx = ldq;
         }
         e = launch_pass(s, pp, w, 1 | (fg ? 0x100 : 0), pass, false, obl, false);
-        if (e == hipSuccess) e = launch_reduce(s, w, pass, E, fg);
+        if (e == hipSuccess) e = launch_reduce(s, w, pass, E, fg, obl_extra_parts(pp, w, 1, obl));
         if (e == hipSuccess && pass < P) e = launch_chol(s, p, w, sp, pass + 1, 0);
     }
     if (e == hipSuccess) e = launch_finalize_r(s, p, w, P);

@@ -538,13 +538,15 @@ __device__ __forceinline__ int chol_inplace(double *G, int S, int n, double s, d
 }
 
 __device__ double shift_value(const SchedParams &sp, int64_t m, int n, double norm2sq,
-                              double bfac, bool oblique, bool f32pass, int f32_chain)
+                              double bfac, bool oblique, bool f32pass, int f32_chain, double sp_depth)
 {
     const double dm = (double)m, dn = (double)n;
     if (f32pass)
         return 11.0 * (((double)f32_chain + 2.0) * dn * kU32 + dn * (dn + 1.0) * kU64) * norm2sq;
     double c;
-    if (sp.shift_mode == SCQR_SHIFT_SMALL)
+    if (sp.shift_mode == SCQR_SHIFT_DEPTH)
+        c = 11.0 * (sp_depth * dn + dn * (dn + 1.0)) * kU64;
+    else if (sp.shift_mode == SCQR_SHIFT_SMALL)
         c = kU64;
     else if (sp.shift_mode == SCQR_SHIFT_CUSTOM)
         c = sp.custom_alpha;
@@ -609,7 +611,10 @@ __device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const
         }
         return;
     }
-    if (threadIdx.x == 0) info->gram_dev[pass - 1] = dev;
+    if (threadIdx.x == 0) {
+        info->gram_dev[pass - 1] = dev;
+        info->gram_depth = p.gram_depth;
+    }
     if (sp.trace) {
         double *tg = sp.trace + (int64_t)(2 * (pass - 1)) * n * n;
         for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
@@ -667,7 +672,7 @@ __device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const
     for (int attempt = 0; attempt < 2; ++attempt) {
         if (try_shift) {
             nrm = norm_estimate();
-            s = shift_value(sp, p.m, n, nrm, bfac, oblique, f32pass, f32_chain_rows(NP));
+            s = shift_value(sp, p.m, n, nrm, bfac, oblique, f32pass, f32_chain_rows(NP), p.gram_depth);
             if (sp.zero_shift) s = 0.0;
             shifted = 1;
             if (f32pass && s > 0.01 * nrm) {

@@ -92,6 +92,15 @@ def test_synchronous_argument_errors(L):
     spd.off = 0x610000000
     assert L.scqr_qr(None, 5000, 30, P, 30, ctypes.byref(spd), 0x900000000, 30, 0x800000000, 30,
                      0x700000000, 1 << 30, ctypes.byref(o2), info) == scqr.E_UNSUPPORTED
+    # the summation-depth shift is Euclidean only
+    o3 = scqr._Opts()
+    L.scqr_default_opts(ctypes.byref(o3))
+    o3.shift_mode = 4
+    assert L.scqr_qr(None, 5000, 30, P, 30, ctypes.byref(spd), 0x900000000, 30, 0x800000000, 30,
+                     0x700000000, 1 << 30, ctypes.byref(o3), info) == scqr.E_UNSUPPORTED
+    o3.shift_mode = 5
+    assert L.scqr_qr(None, 5000, 30, P, 30, None, 0x900000000, 30, 0x800000000, 30,
+                     0x700000000, 1 << 30, ctypes.byref(o3), info) == scqr.E_INVALID
     # backward: dX aliasing Q
     assert L.scqr_qr_backward(None, 5000, 30, P, 30, 0x800000000, 30, None, 30, None, 30, P, 30,
                               0x700000000, 1 << 30) == scqr.E_INVALID
@@ -285,3 +294,35 @@ def test_autotune_candidates_and_cache_io(tmp_path, monkeypatch):
     assert autotune._load_cache(p) == {}
     autotune._store_cache(p, {"k": {"rows_per_task": 2048, "panel_rows": 32}})
     assert autotune._load_cache(p)["k"]["rows_per_task"] == 2048
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # the ctypes mirrors of scqr_opts, scqr_info, scqr_spd_op and scqr_batched_tuning have the
+    # C layout of include/scqr.h (sizes and the offset of every field), checked with the host C
+    # compiler
+    import shutil
+    import subprocess
+
+    import paper_1809_11085_amd as scqr
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    mirrors = {"scqr_opts": scqr._Opts, "scqr_info": scqr._Info, "scqr_spd_op": scqr._SpdOp,
+               "scqr_batched_tuning": scqr._Tuning, "scqr_kernel_stat": scqr._KernelStat}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "scqr.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'printf("{cname}.{f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.splitlines())
+    for cname, py in mirrors.items():
+        assert int(out[cname]) == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert int(out[f"{cname}.{f[0]}"]) == getattr(py, f[0]).offset, (cname, f[0])

@@ -330,3 +330,65 @@ def test_norm_estimate_start_vector_in_small_eigenspace(scqr):
     assert 0.5 * s_paper * (1 - 1e-12) <= info.shift[0] <= 1.0001 * s_paper
     assert info.norm2sq[0] >= 1.0
     assert accuracy.residual(X, host(Q), host(R)) <= 1e-13
+
+
+@pytest.mark.parametrize("m,n,kappa", [(300_000, 64, 1e15), (100_000, 32, 1e13), (50_000, 128, 1e12),
+                                       (20_000, 16, 1e14), (30_000, 256, 1e10)])
+def test_depth_shift_mode(scqr, m, n, kappa):
+    """SCQR_SHIFT_DEPTH: every shift equals 11 (d n + n(n+1)) u lambda_max of that pass's Gram
+    with the depth d the library reports (the power iteration's lower-bound tolerance as for the
+    paper's shift), d is far below m, the result meets the invariants, and it takes no more
+    passes than the paper's shift on the same input."""
+    X = synth.randsvd(m, n, kappa, seed=synth.seed_for(1, 900 + n))
+    Q, R, info = scqr.qr(dev(X), schedule="adaptive", shift="depth", trace=True)
+    assert info.status == scqr.OK, info
+    d = info.gram_depth
+    assert n < d < m / 4
+    tr = info.trace.cpu().numpy()
+    for p in range(info.passes):
+        if info.shifted_mask >> p & 1:
+            lam = np.linalg.eigvalsh(tr[p, 0])[-1]
+            s_exact = oracle.shift_depth(int(d), n, lam)
+            assert info.shift[p] <= s_exact * (1 + 1e-12)
+            assert info.shift[p] >= s_exact * (1 - (1e-4 if p == 0 else 1e-2))
+    Qh, Rh = host(Q), host(R)
+    assert accuracy.orthogonality(Qh)[0] <= 1e-13
+    assert accuracy.residual(X, Qh, Rh) <= 1e-13
+    _, _, ip = scqr.qr(dev(X), schedule="adaptive")
+    assert info.passes <= ip.passes
+    print(f"depth shift m={m} n={n} kappa={kappa:.0e}: d={d:.0f}, passes {info.passes} "
+          f"(paper shift {ip.passes})")
+
+
+def test_depth_bound_holds_for_the_gpu_gram(scqr):
+    # soundness of the reported depth: the GPU Gram is within gamma_d |X|^T |X| of the exact
+    # (rational) Gram, with entries spread over six orders of magnitude
+    from fractions import Fraction
+
+    m, n = 120_000, 3
+    rng = np.random.default_rng(77)
+    X = rng.standard_normal((m, n)) * np.exp(rng.uniform(-7, 7, size=(m, 1)))
+    _, _, info = scqr.qr(dev(X), schedule="cholqr2", shift="depth", trace=True, check="status")
+    G = info.trace.cpu().numpy()[0, 0]
+    d = info.gram_depth
+    g = d * U / (1 - d * U)
+    absg = np.abs(X).T @ np.abs(X)
+    Xf = [[Fraction(v) for v in row] for row in X]
+    for i in range(n):
+        for j in range(i, n):
+            exact = sum(r[i] * r[j] for r in Xf)
+            assert abs(Fraction(G[i, j]) - exact) <= Fraction(g * absg[i, j]), (i, j)
+
+
+def test_depth_shift_batched(scqr):
+    shapes = [(60_000, 64, 1e15), (20_000, 32, 1e12), (8_000, 128, 1e13), (3000, 16, 1e9)]
+    Xs = [synth.randsvd(m, n, k, seed=synth.seed_for(4, 300 + i)) for i, (m, n, k) in enumerate(shapes)]
+    Qs, Rs, infos = scqr.qr_batched([dev(X) for X in Xs], schedule="adaptive", shift="depth")
+    _, _, infp = scqr.qr_batched([dev(X) for X in Xs], schedule="adaptive")
+    for i, X in enumerate(Xs):
+        assert infos[i].status == scqr.OK
+        assert 0 < infos[i].gram_depth < X.shape[0]
+        assert infos[i].passes <= infp[i].passes
+        Qh, Rh = host(Qs[i]), host(Rs[i])
+        assert accuracy.orthogonality(Qh)[0] <= 1e-13
+        assert accuracy.residual(X, Qh, Rh) <= 1e-13
