@@ -642,7 +642,7 @@ scqr_status qr_enqueue(void *stream, int64_t m, int64_t n, const double *X, int6
             pp.ldx = ldq;
         }
         e = launch_pass(s, pp, w, 1 | (fg ? 0x100 : 0), pass, false, obl, false);
-        if (e == hipSuccess) e = launch_reduce(s, w, pass, E, fg, obl_extra_parts(pp, w, 1, obl));
+        if (e == hipSuccess) e = launch_reduce(s, w, pass, E, fg);
         if (e == hipSuccess && pass < P) e = launch_chol(s, p, w, sp, pass + 1, 0);
     }
     if (e == hipSuccess) e = launch_finalize_r(s, p, w, P);

@@ -246,8 +246,7 @@ int64_t pass_partial_elems(int np, bool oblique_first);
 // `pass` selects the predicate on the control block (0 = unconditional, -1 = FP64 redo).
 hipError_t launch_pass(hipStream_t s, const Problem &p, const Work &w, int mode, int pass,
                        bool fp32_gram, bool oblique_gram, bool euclid_too);
-hipError_t launch_reduce(hipStream_t s, const Work &w, int pass, int64_t elems, int final_gram, int extra = 0);
-int obl_extra_parts(const Problem &p, const Work &w, int mode, bool oblique_gram);
+hipError_t launch_reduce(hipStream_t s, const Work &w, int pass, int64_t elems, int final_gram);
 hipError_t launch_chol(hipStream_t s, const Problem &p, const Work &w, const SchedParams &sp,
                        int pass, int variant);
 hipError_t launch_init(hipStream_t s, const Problem &p, const Work &w, const SchedParams &sp);

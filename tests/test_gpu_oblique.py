@@ -89,3 +89,34 @@ def test_oblique_user_bnorm(scqr):
     lam = oracle.lambda_max(oracle.gram(X))
     s_exact = oracle.shift(m, n, lam, bnorm=2000.0, oblique=True)
     assert s_exact * (1 - 1e-4) <= info.shift[0] <= s_exact * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("m,n,kappa", [(64, 64, 1e3), (65, 65, 1e3), (100, 100, 1e4), (4097, 128, 1e10),
+                                       (20000, 96, 1e12), (130_000, 128, 1e13)])
+def test_oblique_fused_pass_gram_replay(scqr, m, n, kappa):
+    """Passes after the first form Q^T B Q of the Q they just wrote.  Replayed pass by pass: the
+    traced B-Gram of pass p >= 2 agrees with the oracle's tridiagonal Gram of the replayed Q (the
+    substitution entry point, bitwise the pass's Q) within 2 gamma_{m+3} |Q|^T |B| |Q|, with
+    shapes of one, two and many 64-row panels, and the last replayed Q equals the factorization's
+    Q bit for bit."""
+    U = 2.0 ** -53
+    X = synth.randsvd(m, n, kappa, seed=synth.seed_for(3, 5 * m + n))
+    d, o = synth.tridiag_b(m, seed=synth.seed_for(3, 11 * n))
+    B = (torch.from_numpy(d).cuda(), torch.from_numpy(o).cuda())
+    Q, R, info = scqr.qr(torch.from_numpy(X).cuda(), B=B, schedule="adaptive", trace=True)
+    assert info.status == scqr.OK, info
+    tr = info.trace.cpu().numpy()
+    Qd = torch.from_numpy(X).cuda()
+    g = (m + 3) * U / (1 - (m + 3) * U)
+    for p in range(info.passes):
+        if p >= 1:
+            Qh = host(Qd)
+            Go = oracle.gram_tridiag(Qh, d, o)
+            absb = oracle.gram_tridiag(np.abs(Qh), np.abs(d), np.abs(o))
+            assert np.all(np.abs(tr[p, 0] - Go) <= 2 * g * absb + 1e-300), f"B-Gram pass {p + 1}"
+            np.testing.assert_array_equal(tr[p, 0], tr[p, 0].T)
+        Qd = scqr.trsm(Qd, torch.from_numpy(np.ascontiguousarray(tr[p, 1])).cuda())
+    np.testing.assert_array_equal(host(Qd), host(Q))
+    Qh, Rh = host(Q), host(R)
+    assert accuracy.orthogonality(Qh, (d, o))[0] <= 1e-13
+    assert accuracy.residual(X, Qh, Rh) <= 1e-13
