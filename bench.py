@@ -44,6 +44,9 @@ WORKLOADS = {
     "c2b": (1 << 22, 64, 1e6, False, "randsvd m=4194304 n=64 kappa=1e6 fp64, adaptive schedule, paper shift"),
     "c1": (4096, 32, 1e12, False, "randsvd m=4096 n=32 kappa=1e12 fp64, adaptive schedule, paper shift"),
     "c3": (1000000, 128, 1e13, True, "randsvd m=1000000 n=128 kappa=1e13, tridiagonal SPD B, fp64"),
+    "c5": (1 << 20, 256, 1e8, False, "randsvd m=1048576 n=256 kappa=1e8 fp64, adaptive schedule, paper shift"),
+    "c4": (0, 0, 0.0, False, "512 instances m_i in [1e4, 2e5], n_i in {16, 32, 64, 128}, kappa_i in [1e4, 1e15], "
+                             "one batched call, fp64"),
 }
 
 
@@ -396,30 +399,59 @@ def extra_c5(scqr, synth):
 
 # short names of the single-problem kernels as the library's profiling records them
 KERNEL_PATTERNS = [
+    # batched: one launch per width class (the class's padded width in the template)
+    ("b_trsm_gram_np", r"k_pass_tile<(\d+), 1, false, (true|false), \d+, true>"),
+    ("b_gram_np", r"k_pass_tile<(\d+), 0, false, (true|false), \d+, true>"),
+    ("b_trsm_gram_np", r"k_pass_wide_b<(\d+)"),
+    ("b_gram_np", r"k_gram_wide<(\d+), false, false, false, true>"),
+    ("b_chol", r"k_chol_b<"),
+    ("b_reduce", r"k_reduce_b\("),
     ("trsm_gram", r"k_pass_tile<\d+, 1, false, (true|false), 32(, false)?>"),
     ("gram", r"k_pass_tile<\d+, 0, false, (true|false), 32(, false)?>"),
     ("trsm_gram", r"k_pass_wide<\d+, 1, (true|false)>"),
     ("trsm", r"k_pass_wide<\d+, 2, (true|false)>"),
+    ("trsm_half1", r"k_pass_wide4<"),
+    ("gram_b_first", r"k_gram_(wide|lds)<\d+, (\d+, )?true, true"),
+    ("gram_b", r"k_gram_(wide|lds)<\d+, (\d+, )?true, false"),
+    ("gram", r"k_gram_(wide|lds)<\d+, (\d+, )?false"),
+    ("rprod", r"k_mm_breg<"),
     ("chol", r"k_chol<\d+>"),
     ("reduce", r"k_reduce_l[12]\("),
     ("finalize_r", r"k_finalize_r<\d+>"),
 ]
 
 
+def alg_bytes(short, m, n, class_mn=None):
+    """Algorithmic HBM bytes of one launch: a fused pass or a substitution reads its input and
+    writes Q (16 m n; 8 m n for the second half of the n = 256 block solve), a Gram reads its
+    input (8 m n; + 16 m for B's two diagonals), the first half of the n = 256 block solve reads
+    X and writes Q_1 and X_2' (16 m n); a batched class launch sums 16 m_i n_i or 8 m_i n_i over
+    the instances of its width class (class_mn[np] = sum of m_i n_i).  None if not modelled."""
+    if short.startswith("b_") and "_np" in short and class_mn is not None:
+        np_ = int(short.rsplit("_np", 1)[1])
+        per = 16 if short.startswith("b_trsm_gram") else 8
+        return per * class_mn.get(np_, 0)
+    return {"trsm_gram": 16 * m * n, "trsm": 16 * m * n if n <= 128 else 8 * m * n, "trsm_half1": 16 * m * n,
+            "gram": 8 * m * n, "gram_b": 8 * m * n + 16 * m, "gram_b_first": 8 * m * n + 16 * m}.get(short)
+
+
 def short_name(kname):
     import re
 
     for short, pat in KERNEL_PATTERNS:
-        if re.search(pat, kname):
-            return short
+        mt = re.search(pat, kname)
+        if mt:
+            # batched class kernels carry their padded width: b_trsm_gram_np64, ...
+            return short + mt.group(1) if short.endswith("_np") else short
     return None
 
 
 def summarize_profile(d, workload):
-    """Summaries of a rocprofv3 kernel trace and of FETCH_SIZE / WRITE_SIZE counter runs of the
-    same bench command, with the counters scaled by what they read for a device copy of known
-    size.  Writes profiles/<kernel>_<workload>.md (text) and _counters.json (read by the
-    roofline object of later runs while the kernel sources are unchanged)."""
+    """Summaries of a rocprofv3 kernel trace and of counter runs of the same bench command:
+    FETCH_SIZE and WRITE_SIZE (scaled by what they read for a device copy of known size) and
+    FP64 MFMA use, for every kernel of the workload that has a short name.  Writes
+    profiles/<kernel>_<workload>.md (text) and _counters.json for the dominant kernel (the
+    roofline object of later runs reads its traffic while the kernel sources are unchanged)."""
     import csv
 
     import numpy as np
@@ -429,6 +461,16 @@ def summarize_profile(d, workload):
             return list(csv.DictReader(fh))
 
     m, n = WORKLOADS[workload][:2]
+    class_mn = None
+    if workload == "c4":
+        import synth
+
+        class_mn = {}
+        for sp in synth.batch_spec(512):
+            np_ = 16
+            while np_ < sp.n:
+                np_ *= 2
+            class_mn[np_] = class_mn.get(np_, 0) + sp.m * sp.n
     trace = rows("trace", "run_kernel_trace.csv")
     stats = rows("trace", "run_kernel_stats.csv")
     per = {}
@@ -437,69 +479,148 @@ def summarize_profile(d, workload):
         if sn:
             per.setdefault(sn, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6)
     dom = max(per, key=lambda k: sum(per[k]))
-    durs = np.array(per[dom])
-    act = durs[durs >= 0.25 * durs.max()]
 
-    def counter(sub):
-        vals = [float(r["Counter_Value"]) for r in rows(sub, "run_counter_collection.csv")
-                if short_name(r["Kernel_Name"]) == dom]
-        v = np.array(vals)
-        return float(np.mean(v[v >= 0.25 * v.max()]))
+    def active(vals, key):
+        top = max(key(v) for v in vals)
+        return [v for v in vals if key(v) >= 0.25 * top]
+
+    def by_kernel(sub):
+        """{short name: {counter: mean over the active dispatches, 'dur': ns}}"""
+        out = {}
+        disp = {}
+        for r in rows(sub, "run_counter_collection.csv"):
+            sn = short_name(r["Kernel_Name"])
+            if not sn:
+                continue
+            dd = disp.setdefault((sn, r["Dispatch_Id"]), {"dur": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+            dd[r["Counter_Name"]] = float(r["Counter_Value"])
+        for (sn, _), v in disp.items():
+            out.setdefault(sn, []).append(v)
+        res = {}
+        for sn, vals in out.items():
+            act = active(vals, lambda v: v["dur"])
+            res[sn] = {k: float(np.mean([v[k] for v in act])) for k in act[0]}
+        return res
 
     def calib(sub):
         v = [float(r["Counter_Value"]) for r in rows(sub, "run_counter_collection.csv")
              if "copyBuffer" in r["Kernel_Name"]]
         return (1 << 30) / 1024.0 / float(np.median(v))
 
-    fetch, write = counter("fetch"), counter("write")
+    fetch, write = by_kernel("fetch"), by_kernel("write")
+    util = by_kernel("util") if os.path.isdir(os.path.join(d, "util")) else {}
     fs, ws = calib("cfetch"), calib("cwrite")
-    traffic = fetch * 1024 * fs + write * 1024 * ws
-    alg = {"trsm_gram": 16 * m * n, "trsm": 16 * m * n, "gram": 8 * m * n}.get(dom, 16 * m * n)
+    kernels = {}
+    for sn, durs in per.items():
+        act = active(durs, lambda x: x)
+        k = {"launches": len(durs), "active_launches": len(act), "avg_active_ms_rocprof": float(np.mean(act))}
+        if sn in fetch and sn in write:
+            f, w_ = fetch[sn]["FETCH_SIZE"], write[sn]["WRITE_SIZE"]
+            k.update({"fetch_kib_per_launch": f, "write_kib_per_launch": w_,
+                      "hbm_bytes_per_launch": f * 1024 * fs + w_ * 1024 * ws})
+        alg = alg_bytes(sn, m, n, class_mn)
+        if alg:
+            k["algorithmic_bytes_per_launch"] = alg
+            k["achieved_GBs"] = alg / (k["avg_active_ms_rocprof"] * 1e-3) / 1e9
+            if "hbm_bytes_per_launch" in k:
+                k["traffic_over_algorithmic"] = k["hbm_bytes_per_launch"] / alg
+        if sn in util:
+            u = util[sn]
+            cycles = u["GRBM_GUI_ACTIVE"] / 8.0
+            k["fp64_mfma"] = {"busy_frac": u["SQ_VALU_MFMA_BUSY_CYCLES"] / (1024.0 * cycles),
+                              "tflops": u["SQ_INSTS_VALU_MFMA_F64"] * 2048.0 / (u["dur"] * 1e-9) / 1e12,
+                              "clock_ghz": cycles / u["dur"],
+                              "lds_bank_conflict_cycles": u.get("SQ_LDS_BANK_CONFLICT")}
+        kernels[sn] = k
     base = "python3 -u bench.py --workload %s --steps 5 --warmup 2 --no-cpu-baseline --no-accuracy --no-extras" % workload
     pdir = os.path.relpath(os.path.abspath(d), ROOT)
     short = base.replace("--steps 5 --warmup 2", "--steps 2 --warmup 1")
     rp = "rocprofv3 %s --output-format csv -d " + pdir + "/%s -o run -- %s"
     cmds = {
         "trace": rp % ("--kernel-trace --stats", "trace", base),
-        "fetch": rp % ("--pmc FETCH_SIZE", "fetch", short),
-        "write": rp % ("--pmc WRITE_SIZE", "write", short),
+        "fetch": rp % ("--kernel-trace --pmc FETCH_SIZE", "fetch", short),
+        "write": rp % ("--kernel-trace --pmc WRITE_SIZE", "write", short),
+        "util": rp % ("--kernel-trace --pmc SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU_MFMA_F64 SQ_LDS_BANK_CONFLICT "
+                      "GRBM_GUI_ACTIVE", "util", short),
         "copy_fetch": rp % ("--pmc FETCH_SIZE", "cfetch", "python3 -u bench.py --copy-calibration"),
         "copy_write": rp % ("--pmc WRITE_SIZE", "cwrite", "python3 -u bench.py --copy-calibration"),
         "summary": "python3 bench.py --workload %s --summarize-profile %s" % (workload, pdir),
     }
+    kd = kernels[dom]
     out = {"kernel": dom, "workload": workload, "source_hash": source_hash(),
-           "avg_active_ms_rocprof": float(np.mean(act)), "active_launches": int(act.size),
-           "fetch_kib_per_launch": fetch, "write_kib_per_launch": write,
-           "fetch_scale": fs, "write_scale": ws, "hbm_bytes_per_launch": traffic,
-           "algorithmic_bytes_per_launch": alg, "traffic_over_algorithmic": traffic / alg,
-           "commands": cmds}
+           "avg_active_ms_rocprof": kd["avg_active_ms_rocprof"], "active_launches": kd["active_launches"],
+           "hbm_bytes_per_launch": kd.get("hbm_bytes_per_launch"),
+           "algorithmic_bytes_per_launch": kd.get("algorithmic_bytes_per_launch"),
+           "fetch_scale": fs, "write_scale": ws, "kernels": kernels, "commands": cmds}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", f"{dom}_{workload}_counters.json"), "w") as fh:
         json.dump(out, fh, indent=1)
-    lines = [f"# rocprofv3 summary: `{dom}` kernel, workload {workload} ({WORKLOADS[workload][4]})", "",
-             "Commands (run from the repository root on one MI355X):", ""]
+    lines = [f"# rocprofv3 summary: workload {workload} ({WORKLOADS[workload][4]})", "",
+             f"Dominant kernel: `{dom}`.  Commands (run from the repository root on one MI355X):", ""]
     lines += [f"* {k}: `{v}`" for k, v in cmds.items()]
     lines += ["", "## Kernel statistics (`--kernel-trace --stats`, run_kernel_stats.csv)", "",
               "| kernel | calls | total ms | avg us | min us | max us |", "|---|---|---|---|---|---|"]
-    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]:
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:14]:
         nm = r["Name"].split("(")[0].replace("|", "/")
         lines.append(f"| `{nm[:70]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} |")
-    lines += ["", f"## `{dom}`", "",
-              f"* launches that ran (duration >= 25% of the longest; the others were skipped by the device "
-              f"schedule): {act.size}, average {np.mean(act) * 1e3:.1f} us, min {act.min() * 1e3:.1f} us, "
-              f"max {act.max() * 1e3:.1f} us",
-              f"* algorithmic bytes per launch: {alg} (16 m n: read X or Q once, write Q once)",
-              f"* FETCH_SIZE {fetch:.1f} KiB and WRITE_SIZE {write:.1f} KiB per launch; a device copy of 1 GiB "
-              f"reads {1048576 / fs:.1f} KiB FETCH_SIZE and {1048576 / ws:.1f} KiB WRITE_SIZE, so the scale "
-              f"factors are {fs:.4f} and {ws:.4f}",
-              f"* HBM traffic per launch: {traffic:.4e} B = {traffic / alg:.4f} x algorithmic",
-              f"* achieved (algorithmic bytes / rocprofv3 average duration): "
-              f"{alg / np.mean(act) / 1e6:.1f} GB/s of 8000 GB/s",
-              f"* source hash of the kernels profiled: {out['source_hash']}", ""]
+    lines += ["", "## Per kernel (launches that ran: duration >= 25% of the longest)", "",
+              "| kernel | active launches | avg us | alg. bytes | achieved GB/s | HBM traffic / alg. | "
+              "FP64 MFMA busy | MFMA TFLOP/s | clock GHz |", "|---|---|---|---|---|---|---|---|---|"]
+
+    def f(v, fmt):
+        return "-" if v is None else format(v, fmt)
+
+    for sn, k in sorted(kernels.items(), key=lambda kv: -kv[1]["avg_active_ms_rocprof"] * kv[1]["active_launches"]):
+        u = k.get("fp64_mfma") or {}
+        lines.append(f"| `{sn}` | {k['active_launches']} | {k['avg_active_ms_rocprof'] * 1e3:.1f} | "
+                     f"{f(k.get('algorithmic_bytes_per_launch'), '.4g')} | {f(k.get('achieved_GBs'), '.0f')} | "
+                     f"{f(k.get('traffic_over_algorithmic'), '.3f')} | {f(u.get('busy_frac'), '.3f')} | "
+                     f"{f(u.get('tflops'), '.1f')} | {f(u.get('clock_ghz'), '.2f')} |")
+    lines += ["", f"A device copy of 1 GiB reads {1048576 / fs:.1f} KiB FETCH_SIZE and {1048576 / ws:.1f} KiB "
+              f"WRITE_SIZE, so the counters are scaled by {fs:.4f} and {ws:.4f}.  MFMA busy is "
+              "SQ_VALU_MFMA_BUSY_CYCLES over the SIMD-cycles of the launch (1024 SIMDs, GRBM_GUI_ACTIVE / 8 "
+              "XCDs cycles); MFMA TFLOP/s counts 2048 flops per FP64 16x16x4 instruction.",
+              f"Source hash of the kernels profiled: {out['source_hash']}", ""]
     with open(os.path.join(ROOT, "profiles", f"{dom}_{workload}.md"), "w") as fh:
         fh.write("\n".join(lines))
-    print(json.dumps(out))
+    print(json.dumps({"kernel": dom, "kernels": kernels}))
+
+
+def run_batched(args, scqr, synth):
+    """--workload c4: the 512-instance batch, all FP64, one batched call per step (for profiling
+    the per-class launches); one JSON line with the step time and the per-kernel event times."""
+    import numpy as np
+    import torch
+
+    spec = synth.batch_spec(512)
+    shapes = [(s_.m, s_.n) for s_ in spec]
+    Xs = [torch.from_numpy(synth.randsvd(s_.m, s_.n, s_.kappa, seed=s_.seed)).cuda() for s_ in spec]
+    bp = scqr.BatchedPlan(shapes, "cuda")
+    for _ in range(args.warmup):
+        bp.run(Xs)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(args.steps):
+        bp.run(Xs)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    infos = bp.read_infos()
+    fl = sum(flops_of(m, n, i.passes) for (m, n), i in zip(shapes, infos))
+    scqr.profile_enable(True)
+    bp.run(Xs)
+    torch.cuda.synchronize()
+    recs = scqr.profile_read()
+    scqr.profile_enable(False)
+    by = {}
+    for name, dur in recs:
+        by.setdefault(name, []).append(dur)
+    print(json.dumps({"workload": WORKLOADS["c4"][4], "ms_per_step": round(ms, 4), "TFLOP/s": round(fl / ms / 1e9, 3),
+                      "ok": sum(1 for i in infos if i.status == scqr.OK),
+                      "kernels_ms": {k: round(float(np.sum(v)), 4) for k, v in by.items()}}), flush=True)
 
 
 def main():
@@ -545,8 +666,11 @@ def main():
         from paper_1809_11085_amd import build as hipbuild
         hipbuild.build()
     torch.cuda.set_device(0)
+    if args.workload == "c4":
+        run_batched(args, scqr, synth)
+        return
     m, n, kappa, oblique, desc = WORKLOADS[args.workload]
-    cfg_index = {"c1": 0, "c2": 1, "c2b": 1, "c3": 2}[args.workload]
+    cfg_index = {"c1": 0, "c2": 1, "c2b": 1, "c3": 2, "c5": 4}[args.workload]
     t = time.perf_counter()
     X = synth.randsvd(m, n, kappa, seed=synth.seed_for(cfg_index))
     B = None
