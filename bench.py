@@ -45,6 +45,8 @@ WORKLOADS = {
     "c1": (4096, 32, 1e12, False, "randsvd m=4096 n=32 kappa=1e12 fp64, adaptive schedule, paper shift"),
     "c3": (1000000, 128, 1e13, True, "randsvd m=1000000 n=128 kappa=1e13, tridiagonal SPD B, fp64"),
     "c5": (1 << 20, 256, 1e8, False, "randsvd m=1048576 n=256 kappa=1e8 fp64, adaptive schedule, paper shift"),
+    "f3": (1 << 23, 32, 1e15, False, "randsvd m=8388608 n=32 kappa=1e15 fp64, adaptive schedule, paper shift, "
+                                     "minimum-traffic passes"),
     "c4": (0, 0, 0.0, False, "512 instances m_i in [1e4, 2e5], n_i in {16, 32, 64, 128}, kappa_i in [1e4, 1e15], "
                              "one batched call, fp64"),
 }
@@ -242,6 +244,39 @@ def extra_f2(scqr, synth):
     return out
 
 
+def extra_f3(scqr, synth):
+    """Minimum-traffic passes (n <= 32): the stored schedule (each pass reads the previous Q and
+    writes its own, 8 (2p + 1) m n bytes for p passes) against the recomputing one (passes
+    before the last read X and write nothing, 8 (p + 2) m n bytes), on 2^23 rows at n = 32 and
+    16, and whether the two give the same factors bit for bit."""
+    import torch
+
+    m = 1 << 23
+    out = {}
+    for n, kappa, sched in ((32, 1e15, "adaptive"), (32, 1e12, "fixed3"), (16, 1e15, "adaptive")):
+        X = torch.from_numpy(synth.randsvd(m, n, kappa, seed=synth.seed_for(9, n))).cuda()
+        r, fac = {}, {}
+        for mt in (False, True):
+            key = "recompute" if mt else "stored"
+            plan = scqr.Plan(m, n, "cuda", schedule=sched, recompute=mt)
+            ms = _time_ms(lambda: plan.run(X), reps=5)
+            info = plan.read_info()
+            p = info.passes
+            nb = 8 * (p + 2) * m * n if mt else 8 * (2 * p + 1) * m * n
+            r[key] = {"ms": round(ms, 4), "passes": p, "status": scqr.status_string(info.status),
+                      "model_bytes": nb, "GB/s": round(nb / ms / 1e6, 1),
+                      "TFLOP/s": round(flops_of(m, n, p) / ms / 1e9, 3)}
+            fac[key] = (plan.Q.clone(), plan.R.clone())
+            del plan
+        r["bitwise_equal"] = bool(torch.equal(fac["stored"][0], fac["recompute"][0]) and
+                                  torch.equal(fac["stored"][1], fac["recompute"][1]))
+        r["speedup_recompute_vs_stored"] = round(r["stored"]["ms"] / r["recompute"]["ms"], 3)
+        out[f"m=2^23 n={n} kappa={kappa:.0e} {sched}"] = r
+        del X, fac
+        torch.cuda.empty_cache()
+    return out
+
+
 def extra_c3(scqr, synth):
     import torch
 
@@ -407,6 +442,7 @@ KERNEL_PATTERNS = [
     ("b_chol", r"k_chol_b<"),
     ("b_reduce", r"k_reduce_b\("),
     ("trsm_gram", r"k_pass_tile<\d+, 1, false, (true|false), 32(, false)?>"),
+    ("trsm_gram_mt", r"k_pass_tile<\d+, 5, false, (true|false), 32(, false)?>"),
     ("gram", r"k_pass_tile<\d+, 0, false, (true|false), 32(, false)?>"),
     ("trsm_gram", r"k_pass_wide<\d+, 1, (true|false)>"),
     ("trsm", r"k_pass_wide<\d+, 2, (true|false)>"),
@@ -577,6 +613,30 @@ def summarize_profile(d, workload):
                      f"{f(k.get('algorithmic_bytes_per_launch'), '.4g')} | {f(k.get('achieved_GBs'), '.0f')} | "
                      f"{f(k.get('traffic_over_algorithmic'), '.3f')} | {f(u.get('busy_frac'), '.3f')} | "
                      f"{f(u.get('tflops'), '.1f')} | {f(u.get('clock_ghz'), '.2f')} |")
+    if "trsm_gram_mt" in kernels:
+        # one kernel for every pass: before the last it reads X and writes nothing (8 m n), the
+        # last pass also writes Q (16 m n); listed launch by launch in dispatch order
+        def per_dispatch(sub, cname):
+            v = {}
+            for r in rows(sub, "run_counter_collection.csv"):
+                if short_name(r["Kernel_Name"]) == "trsm_gram_mt" and r["Counter_Name"] == cname:
+                    v[int(r["Dispatch_Id"])] = (float(r["Counter_Value"]),
+                                                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6)
+            return [v[k] for k in sorted(v)]
+        fd, wd = per_dispatch("fetch", "FETCH_SIZE"), per_dispatch("write", "WRITE_SIZE")
+        seq = [{"read_bytes": fv * 1024 * fs, "written_bytes": wv * 1024 * ws, "ms": fdur}
+               for (fv, fdur), (wv, _) in zip(fd, wd)]
+        seq = seq[-6:]  # the last factorization: passes 1 .. max_passes = 6 (later ones gated off)
+        kernels["trsm_gram_mt"]["per_launch"] = seq
+        lines += ["", "## Minimum-traffic passes, launch by launch (`trsm_gram_mt`, counter runs)", "",
+                  "The last factorization of each counter run, passes 1 to 6 (a pass after the last one "
+                  "returns at once).",
+                  f"Model: 8 m n = {8 * m * n:.4g} bytes read per pass; the last pass also writes 8 m n.", "",
+                  "| launch | ms (counter run) | HBM read bytes | HBM written bytes | read / 8mn | written / 8mn |",
+                  "|---|---|---|---|---|---|"]
+        for i, e in enumerate(seq):
+            lines.append(f"| {i + 1} | {e['ms']:.3f} | {e['read_bytes']:.4g} | {e['written_bytes']:.4g} | "
+                         f"{e['read_bytes'] / (8 * m * n):.3f} | {e['written_bytes'] / (8 * m * n):.3f} |")
     lines += ["", f"A device copy of 1 GiB reads {1048576 / fs:.1f} KiB FETCH_SIZE and {1048576 / ws:.1f} KiB "
               f"WRITE_SIZE, so the counters are scaled by {fs:.4f} and {ws:.4f}.  MFMA busy is "
               "SQ_VALU_MFMA_BUSY_CYCLES over the SIMD-cycles of the launch (1024 SIMDs, GRBM_GUI_ACTIVE / 8 "
@@ -638,7 +698,7 @@ def main():
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="write profiles/<kernel>_<workload>.md and _counters.json from the rocprofv3 "
                          "outputs under DIR (trace/, fetch/, write/, cfetch/, cwrite/)")
-    ap.add_argument("--extras", default="c2b,f2,c3,c4,c5")
+    ap.add_argument("--extras", default="c2b,f2,f3,c3,c4,c5")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -670,9 +730,12 @@ def main():
         run_batched(args, scqr, synth)
         return
     m, n, kappa, oblique, desc = WORKLOADS[args.workload]
-    cfg_index = {"c1": 0, "c2": 1, "c2b": 1, "c3": 2, "c5": 4}[args.workload]
     t = time.perf_counter()
-    X = synth.randsvd(m, n, kappa, seed=synth.seed_for(cfg_index))
+    if args.workload == "f3":
+        X = synth.randsvd(m, n, kappa, seed=synth.seed_for(9, n))
+    else:
+        cfg_index = {"c1": 0, "c2": 1, "c2b": 1, "c3": 2, "c5": 4}[args.workload]
+        X = synth.randsvd(m, n, kappa, seed=synth.seed_for(cfg_index))
     B = None
     if oblique:
         d, o = synth.tridiag_b(m, seed=synth.seed_for(cfg_index, 1))
@@ -680,7 +743,8 @@ def main():
     Xd = torch.from_numpy(X).cuda()
     log(f"[bench] generated {args.workload} {m}x{n} kappa={kappa:.0e} in {time.perf_counter() - t:.1f} s")
 
-    plan = scqr.Plan(m, n, "cuda", B=B, schedule="adaptive", shift="paper", max_passes=6)
+    plan = scqr.Plan(m, n, "cuda", B=B, schedule="adaptive", shift="paper", max_passes=6,
+                     recompute=args.workload == "f3")
     for _ in range(args.warmup):
         plan.run(Xd)
     torch.cuda.synchronize()
@@ -783,7 +847,8 @@ def main():
         result["cpu_baseline"]["value"] = round(cb["value"], 5)
         log(f"[bench] cpu baseline: {cb['value'] * 1e3:.2f} GFLOP/s on {cb['cores']} threads")
     if args.workload == "c2" and not args.no_extras:
-        fns = {"c2b": extra_c2b, "f2": extra_f2, "c3": extra_c3, "c4": extra_c4, "c5": extra_c5}
+        fns = {"c2b": extra_c2b, "f2": extra_f2, "f3": extra_f3, "c3": extra_c3, "c4": extra_c4,
+               "c5": extra_c5}
         extras, speed = {}, {}
         for name in [x for x in args.extras.split(",") if x]:
             t = time.perf_counter()
@@ -796,6 +861,9 @@ def main():
                           ("c2b", "speedup_cholqr2_vs_scholqr3"), ("f2", "speedup_depth_vs_paper_shift")):
             if key in extras.get(name, {}):
                 speed[f"{name}_{key[8:]}"] = extras[name][key]
+        for wl, r in extras.get("f3", {}).items():
+            if isinstance(r, dict) and "speedup_recompute_vs_stored" in r:
+                speed[f"f3_recompute_vs_stored {wl}"] = r["speedup_recompute_vs_stored"]
         result["speedups"] = speed
         result["extras"] = extras
     print(json.dumps(result), flush=True)

@@ -94,7 +94,17 @@ typedef struct {
     int32_t final_gram;     /* 1: also form the Gram of the final Q and report omega_fro      */
     int32_t debug_force_breakdown_pass; /* >0: the Cholesky of that pass reports breakdown    */
     int32_t debug_zero_shift;           /* 1: every shift is zero                             */
-    int32_t reserved;
+    int32_t recompute;      /* 1: minimum-traffic passes (n <= 32, B = I; not in the paper).  A
+                               pass before the last recomputes its input Q from X through the
+                               factors of the earlier passes instead of reading a stored Q, and
+                               writes no Q; only the last pass writes Q.  HBM traffic
+                               8 (p + 2) m n bytes for p passes instead of 8 (2 p + 1) m n, at
+                               p (p - 1) / 2 extra substitutions; Q, R and info equal those of
+                               the default (0: each pass stores Q) bit for bit.  X is read by
+                               every pass, so it must not change until the call completes (Q
+                               may still alias X).  After a breakdown or a non-finite Gram
+                               Q is not written (the default leaves the last completed pass's
+                               Q).  Other shapes and the batched call: SCQR_E_UNSUPPORTED. */
     double custom_alpha;    /* SCQR_SHIFT_CUSTOM: s = custom_alpha ||X||_2^2 (||B||_2)        */
     double bnorm;           /* > 0: caller's bound on ||B||_2; else the Gershgorin bound      */
     double *trace;          /* nullable device buffer of max_passes * 2 * n * n doubles: for

@@ -64,7 +64,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("shift_mode", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("max_passes", ctypes.c_int32),
                 ("final_gram", ctypes.c_int32), ("debug_force_breakdown_pass", ctypes.c_int32),
-                ("debug_zero_shift", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("debug_zero_shift", ctypes.c_int32), ("recompute", ctypes.c_int32),
                 ("custom_alpha", ctypes.c_double), ("bnorm", ctypes.c_double),
                 ("trace", ctypes.c_void_p)]
 
@@ -183,7 +183,7 @@ def _workspace(nbytes: int, dev) -> tuple:
 
 def _opts(schedule="adaptive", shift="paper", precision="fp64", max_passes=6, final_gram=False,
           custom_alpha=0.0, bnorm=0.0, trace_ptr=None, debug_force_breakdown_pass=0,
-          debug_zero_shift=False) -> _Opts:
+          debug_zero_shift=False, recompute=False) -> _Opts:
     o = _Opts()
     lib().scqr_default_opts(ctypes.byref(o))
     o.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
@@ -196,6 +196,7 @@ def _opts(schedule="adaptive", shift="paper", precision="fp64", max_passes=6, fi
     o.trace = trace_ptr
     o.debug_force_breakdown_pass = int(debug_force_breakdown_pass)
     o.debug_zero_shift = int(bool(debug_zero_shift))
+    o.recompute = int(bool(recompute))
     return o
 
 
@@ -289,7 +290,9 @@ def qr(X: torch.Tensor, B=None, *, inplace=False, check=True, trace=False, **opt
     inspects ``info.status``; False returns the raw device record without synchronizing.
     ``B = (diag, off)`` selects the oblique inner product with a tridiagonal SPD B.
     ``trace=True`` also returns per-pass input Grams and triangular factors in ``info.trace``
-    (shape [passes, 2, n, n])."""
+    (shape [passes, 2, n, n]).  ``recompute=True`` (n <= 32, B = I) selects the minimum-traffic
+    passes: each pass before the last recomputes its input from X instead of reading a stored
+    Q, and only the last pass writes Q (same results bit for bit)."""
     mode = check_mode(check)
     m, n = X.shape
     tr = None

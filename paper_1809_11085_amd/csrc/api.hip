@@ -85,6 +85,7 @@ scqr_status check_opts(const scqr_opts *o)
     if (o->precision < 0 || o->precision > 1) return SCQR_E_INVALID;
     if (o->max_passes < 1 || o->max_passes > SCQR_MAX_PASSES) return SCQR_E_INVALID;
     if (o->shift_mode == SCQR_SHIFT_CUSTOM && !(o->custom_alpha >= 0.0)) return SCQR_E_INVALID;
+    if (o->recompute < 0 || o->recompute > 1) return SCQR_E_INVALID;
     return SCQR_OK;
 }
 
@@ -224,6 +225,7 @@ scqr_status plan_batch(int32_t batch, const int64_t *m, const int64_t *n, const 
 {
     scqr_status st = check_opts(&o);
     if (st != SCQR_OK) return st;
+    if (o.recompute) return SCQR_E_UNSUPPORTED;
     st = check_tuning(tune);
     if (st != SCQR_OK) return st;
     for (int32_t i = 0; i < batch; ++i) {
@@ -580,6 +582,8 @@ scqr_status qr_enqueue(void *stream, int64_t m, int64_t n, const double *X, int6
     const bool obl = is_oblique(B);
     if (obl && o.precision == SCQR_PREC_FP32_FIRST) return SCQR_E_UNSUPPORTED;
     if (obl && o.shift_mode == SCQR_SHIFT_DEPTH) return SCQR_E_UNSUPPORTED;
+    const bool mt = o.recompute == 1;
+    if (mt && (obl || n > 32)) return SCQR_E_UNSUPPORTED;
     // aliasing: Q may equal X exactly; R must not overlap X, Q or the workspace
     const size_t xb = mat_bytes(m, n, ldx), qb = mat_bytes(m, n, ldq), rb = mat_bytes(n, n, ldr);
     if (Q != X && ranges_overlap(X, xb, Q, qb)) return SCQR_E_INVALID;
@@ -636,12 +640,13 @@ scqr_status qr_enqueue(void *stream, int64_t m, int64_t n, const double *X, int6
     }
     const int P = o.schedule == SCQR_SCHED_FIXED3 ? 3 : o.schedule == SCQR_SCHED_CHOLQR2 ? 2 : o.max_passes;
     for (int pass = 1; pass <= P && e == hipSuccess; ++pass) {
+        // stored passes read the previous pass's Q; minimum-traffic passes read X every time
         Problem pp = p;
-        if (pass > 1) {
+        if (pass > 1 && !mt) {
             pp.X = Q;
             pp.ldx = ldq;
         }
-        e = launch_pass(s, pp, w, 1 | (fg ? 0x100 : 0), pass, false, obl, false);
+        e = launch_pass(s, pp, w, (mt ? 5 : 1) | (fg ? 0x100 : 0), pass, false, obl, false);
         if (e == hipSuccess) e = launch_reduce(s, w, pass, E, fg);
         if (e == hipSuccess && pass < P) e = launch_chol(s, p, w, sp, pass + 1, 0);
     }

@@ -48,6 +48,10 @@ __device__ __forceinline__ void wave_sync()
 // The solved panel then feeds the FP64 MFMA Gram (all upper 16x16 tiles in registers).
 //   MODE 0: Gram of X only.  MODE 1: TRSM + Gram.  MODE 2: TRSM only.  MODE 3: the transposed
 //   solve x R~^T = y row by row (back substitution in blocked order, for the QR adjoint).
+//   MODE 5 (minimum traffic, NP <= 32): Rt and dinv are the factor history; the panel of X is
+//   solved against the factors of passes 1 .. pass in turn, exactly as the stored-Q passes
+//   solve it one pass at a time, so the panel equals that pass's Q bit for bit.  Q is written
+//   only when this pass is the last one; the Gram follows as in MODE 1.
 //   F32: Gram in binary32 MFMA, each panel (one chain of f32_chain_rows(NP) = PR rows) added to the
 //        binary64 tiles after the panel (MODE 0 only).
 //   VEC: n even, even leading dimensions and 16-byte aligned X, Q (pairs of doubles per access).
@@ -102,12 +106,21 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
     static_assert((PR * NP / 2) % 64 == 0, "panel must split evenly over a wave");
     static_assert(PR % 32 == 0, "Gram row mapping covers 32-row blocks");
     static_assert(!F32 || PR == f32_chain_rows(NP), "a binary32 chain is one panel");
-    constexpr int BL = (MODE >= 1 && NOFF > 0) ? NOFF * 4 * 64 : 1;
+    // MODE 5 holds -R~_KJ of every factor it applies (one per pass up to this one) in dynamic
+    // LDS of pass * BLF doubles
+    static_assert(MODE != 5 || (NP <= 32 && !BATCH && !F32), "minimum-traffic passes: n <= 32, one problem");
+    constexpr int BLF = NOFF * 4 * 64;
+    constexpr int BL = (MODE >= 1 && MODE != 5 && NOFF > 0) ? BLF : 1;
     __shared__ __attribute__((aligned(16))) double lds[LDSZ];
-    __shared__ double bl[BL];
+    __shared__ double bl_s[BL];
+    extern __shared__ double bl_dyn[];
+    double *const bl = MODE == 5 ? bl_dyn : bl_s;
 
     if (!gate(ctl, pass)) return;
-    const bool want_gram = (MODE == 0) || (MODE == 1 && gram_needed(ctl, pass, final_gram));
+    const bool want_gram = (MODE == 0) || ((MODE == 1 || MODE == 5) && gram_needed(ctl, pass, final_gram));
+    // factors applied to each panel, and whether the panel is stored
+    const int nfac = MODE == 5 ? pass : 1;
+    const bool store_q = MODE != 5 || ctl->last == pass;
 
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -122,17 +135,19 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
 
     // -R~_KJ (K < J) in the B-operand layout, one 64-entry vector per (block pair, k-step):
     // entry l holds -r[16K + 4s + l/16][16J + l%16].
-    if (MODE >= 1 && NOFF > 0) {
-        for (int idx = threadIdx.x; idx < NOFF * 4 * 64; idx += WAVES * 64) {
-            const int l = idx & 63, s4 = (idx >> 6) & 3, pi = idx >> 8;
+    if constexpr (MODE >= 1 && NOFF > 0) {
+        for (int idx = threadIdx.x; idx < BLF * nfac; idx += WAVES * 64) {
+            const int f = idx / BLF;  // factor (MODE 5); 0 otherwise
+            const int l = idx & 63, s4 = (idx >> 6) & 3, pi = (idx - f * BLF) >> 8;
             int J = 1, K = pi;
             while (K >= J) {
                 K -= J;
                 ++J;
             }
             // MODE 3 uses the transposed blocks: entry l holds -r[16K + l%16][16J + 4s + l/16]
-            const int e = MODE == 3 ? (16 * K + (l & 15)) * NP + 16 * J + 4 * s4 + (l >> 4)
-                                    : (16 * K + 4 * s4 + (l >> 4)) * NP + 16 * J + (l & 15);
+            const int e = f * NP * NP +
+                          (MODE == 3 ? (16 * K + (l & 15)) * NP + 16 * J + 4 * s4 + (l >> 4)
+                                     : (16 * K + 4 * s4 + (l >> 4)) * NP + 16 * J + (l & 15));
             bl[idx] = -(BATCH ? as_cview(Rt)[e] : Rt[e]);
         }
         __syncthreads();
@@ -247,86 +262,93 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
                     wave_sync();
                 }
             } else {
-            int pi0 = 0;
+            // MODE 5: factors 1 .. pass in turn (a runtime loop around the same blocked solve)
+            for (int f = 0; f < nfac; ++f) {
+                const double *Rtf = Rt + f * (NP * NP);
+                const double *dvf = dinv + f * NP;
+                const double *blf = bl + f * BLF;
+                int pi0 = 0;
 #pragma unroll
-            for (int J = 0; J < NT; ++J) {
-                if (J > 0) {
+                for (int J = 0; J < NT; ++J) {
+                    if (J > 0) {
 #pragma unroll
-                    for (int g = 0; g < PR / 16; ++g) {
-                        double *blk = P + (16 * g + plk) * S + 16 * J + li;
-                        d4 d;
+                        for (int g = 0; g < PR / 16; ++g) {
+                            double *blk = P + (16 * g + plk) * S + 16 * J + li;
+                            d4 d;
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) d[r] = blk[r * S];
-                        const double *arow = P + (16 * g + pli) * S + lk;
-                        int pi = pi0;
+                            for (int r = 0; r < 4; ++r) d[r] = blk[r * S];
+                            const double *arow = P + (16 * g + pli) * S + lk;
+                            int pi = pi0;
 #pragma unroll
-                        for (int K = 0; K < J; ++K, ++pi)
+                            for (int K = 0; K < J; ++K, ++pi)
 #pragma unroll
-                            for (int s4 = 0; s4 < 4; ++s4)
-                                d = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * K + 4 * s4],
-                                                                         bl[(pi * 4 + s4) * 64 + lane], d, 0, 0, 0);
+                                for (int s4 = 0; s4 < 4; ++s4)
+                                    d = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * K + 4 * s4],
+                                                                             blf[(pi * 4 + s4) * 64 + lane], d, 0, 0, 0);
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) blk[r * S] = d[r];
+                            for (int r = 0; r < 4; ++r) blk[r * S] = d[r];
+                        }
+                        pi0 += J;
+                        wave_sync();
                     }
-                    pi0 += J;
+                    if (lane < PR) {
+                        double *mr = P + lane * S + 16 * J;
+                        double t[16];
+#pragma unroll
+                        for (int c = 0; c < 16; c += 2) {
+                            const double2 v = *reinterpret_cast<const double2 *>(mr + c);
+                            t[c] = v.x;
+                            t[c + 1] = v.y;
+                        }
+                        int64_t offk = off;
+#pragma unroll
+                        for (int k = 0; k < 16; ++k) {
+                            // re-laundered every two rows: later rows' scalar loads may not be
+                            // hoisted above earlier rows' work (they would exhaust the SGPRs)
+                            if ((k & 1) == 0) asm volatile("" : "+s"(offk));
+                            if constexpr (BATCH) {
+                                const cview<double> Rd = as_cview(Rtf) + offk + (16 * J) * NP + 16 * J;
+                                const double qk = t[k] * as_cview(dvf)[offk + 16 * J + k];
+                                t[k] = qk;
+#pragma unroll
+                                for (int j = k + 1; j < 16; ++j) t[j] = __builtin_fma(-qk, Rd[k * NP + j], t[j]);
+                            } else {
+                                const double *Rd = Rtf + offk + (16 * J) * NP + 16 * J;
+                                const double qk = t[k] * dvf[offk + 16 * J + k];
+                                t[k] = qk;
+#pragma unroll
+                                for (int j = k + 1; j < 16; ++j) t[j] = __builtin_fma(-qk, Rd[k * NP + j], t[j]);
+                            }
+                        }
+#pragma unroll
+                        for (int c = 0; c < 16; c += 2) *reinterpret_cast<double2 *>(mr + c) = make_double2(t[c], t[c + 1]);
+                    }
                     wave_sync();
                 }
-                if (lane < PR) {
-                    double *mr = P + lane * S + 16 * J;
-                    double t[16];
-#pragma unroll
-                    for (int c = 0; c < 16; c += 2) {
-                        const double2 v = *reinterpret_cast<const double2 *>(mr + c);
-                        t[c] = v.x;
-                        t[c + 1] = v.y;
-                    }
-                    int64_t offk = off;
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) {
-                        // re-laundered every two rows: later rows' scalar loads may not be
-                        // hoisted above earlier rows' work (they would exhaust the SGPRs)
-                        if ((k & 1) == 0) asm volatile("" : "+s"(offk));
-                        if constexpr (BATCH) {
-                            const cview<double> Rd = as_cview(Rt) + offk + (16 * J) * NP + 16 * J;
-                            const double qk = t[k] * as_cview(dinv)[offk + 16 * J + k];
-                            t[k] = qk;
-#pragma unroll
-                            for (int j = k + 1; j < 16; ++j) t[j] = __builtin_fma(-qk, Rd[k * NP + j], t[j]);
-                        } else {
-                            const double *Rd = Rt + offk + (16 * J) * NP + 16 * J;
-                            const double qk = t[k] * dinv[offk + 16 * J + k];
-                            t[k] = qk;
-#pragma unroll
-                            for (int j = k + 1; j < 16; ++j) t[j] = __builtin_fma(-qk, Rd[k * NP + j], t[j]);
-                        }
-                    }
-#pragma unroll
-                    for (int c = 0; c < 16; c += 2) *reinterpret_cast<double2 *>(mr + c) = make_double2(t[c], t[c + 1]);
-                }
-                wave_sync();
             }
             }
             // ---- Q panel -> HBM
-            if constexpr (VEC) {
-                const __amdgpu_buffer_rsrc_t rq = rows_rsrc(Qout, p.ldq, r0, p.m, n);
-                const uint32_t offq = cl < n ? (uint32_t)((rl * p.ldq + cl) * 8) : kBufOut;
-                const uint32_t dqs = (uint32_t)(RSTEP * p.ldq * 8);
+            if (store_q) {
+                if constexpr (VEC) {
+                    const __amdgpu_buffer_rsrc_t rq = rows_rsrc(Qout, p.ldq, r0, p.m, n);
+                    const uint32_t offq = cl < n ? (uint32_t)((rl * p.ldq + cl) * 8) : kBufOut;
+                    const uint32_t dqs = (uint32_t)(RSTEP * p.ldq * 8);
 #pragma unroll
-                for (int i = 0; i < PP; ++i)
-                    buf_store2(rq, offq + (uint32_t)i * dqs,
-                               *reinterpret_cast<const double2 *>(P + (rl + RSTEP * i) * S + cl));
-            } else
+                    for (int i = 0; i < PP; ++i)
+                        buf_store2(rq, offq + (uint32_t)i * dqs,
+                                   *reinterpret_cast<const double2 *>(P + (rl + RSTEP * i) * S + cl));
+                } else {
 #pragma unroll
-            for (int i = 0; i < PP; ++i) {
-                const int e2 = lane + 64 * i;
-                const int r = e2 / (NP / 2), c = 2 * (e2 % (NP / 2));
-                const int64_t row = r0 + r;
-                if (row < p.m && c < n) {
-                    const double2 v = *reinterpret_cast<const double2 *>(P + r * S + c);
-                    double *dst = Qout + row * p.ldq + c;
-                    {
-                        dst[0] = v.x;
-                        if (c + 1 < n) dst[1] = v.y;
+                    for (int i = 0; i < PP; ++i) {
+                        const int e2 = lane + 64 * i;
+                        const int r = e2 / (NP / 2), c = 2 * (e2 % (NP / 2));
+                        const int64_t row = r0 + r;
+                        if (row < p.m && c < n) {
+                            const double2 v = *reinterpret_cast<const double2 *>(P + r * S + c);
+                            double *dst = Qout + row * p.ldq + c;
+                            dst[0] = v.x;
+                            if (c + 1 < n) dst[1] = v.y;
+                        }
                     }
                 }
             }
@@ -1567,6 +1589,15 @@ static bool uses_small(int np, bool oblique) { return np <= 64 && !oblique; }
 int pass_grid(int64_t m, int np)
 {
     const int cus = cu_count();
+    if (np <= 32) {
+        // workgroups of 4 waves on 64-row panels, persistent over the panels; two (n <= 32)
+        // or four (n <= 16) fit a CU's LDS
+        const int64_t panels = (m + 63) / 64;
+        int64_t wg = (panels + 3) / 4;
+        const int64_t cap = (np <= 16 ? 4 : 2) * (int64_t)cus;
+        if (wg > cap) wg = cap;
+        return (int)(wg < 1 ? 1 : wg);
+    }
     if (np <= 64) {
         // one workgroup of 8 waves (32-row panels) per CU, persistent over the panels
         const int64_t panels = (m + 31) / 32;
@@ -1588,25 +1619,41 @@ int64_t pass_partial_elems(int np, bool oblique_first)
     return oblique_first ? 2 * e : e;
 }
 
-// Rows per panel of the fused kernel (64: 4 waves per workgroup, 32: 8 waves).
+// Rows per panel of the fused kernel (64: 4 waves per workgroup, 32: 8 waves): 32 for the
+// batched binary32 Gram (one panel is one binary32 chain) and the adjoint's transposed solve.
 constexpr int kPanelRows = 32;
+// Single problem: 64 for n <= 32, where one row per lane keeps all 64 lanes busy in the
+// diagonal-block substitution; 32 for n <= 64, where a 64-row panel would not fit a wave's
+// registers.  The binary32 Gram keeps its 32-row chains.
+template <int NP>
+constexpr int single_panel_rows() { return NP <= 32 ? 64 : 32; }
 
 template <int NP, bool VEC>
 static void launch_small_v(hipStream_t s, const Problem &p, const Work &w, int mode, int pass,
                            bool f32, int final_gram)
 {
-    constexpr int PR = kPanelRows;
+    constexpr int PR = single_panel_rows<NP>();
     dim3 grid(w.nwg), block(PR == 64 ? 256 : 512);
     if (mode == 0) {
         if (f32)
-            hipLaunchKernelGGL((k_pass_tile<NP, 0, true, VEC, PR, false>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
-                               w.partials, w.ctl, pass, final_gram, nullptr, nullptr);
+            hipLaunchKernelGGL((k_pass_tile<NP, 0, true, VEC, f32_chain_rows(NP), false>), grid,
+                               dim3(f32_chain_rows(NP) == 64 ? 256 : 512), 0, s, p, p.Q, factor_of(w, NP, pass),
+                               dinv_of(w, NP, pass), w.partials, w.ctl, pass, final_gram, nullptr, nullptr);
         else
             hipLaunchKernelGGL((k_pass_tile<NP, 0, false, VEC, PR, false>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
                                w.partials, w.ctl, pass, final_gram, nullptr, nullptr);
     } else if (mode == 1) {
         hipLaunchKernelGGL((k_pass_tile<NP, 1, false, VEC, PR, false>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
                            w.partials, w.ctl, pass, final_gram, nullptr, nullptr);
+    } else if (mode == 5) {
+        // minimum traffic: the whole factor history, passes 1 .. pass
+        if constexpr (NP <= 32) {
+            constexpr int nt = NP / 16;
+            const size_t dyn = sizeof(double) * (size_t)(nt * (nt - 1) / 2) * 256 * (size_t)pass;
+            hipLaunchKernelGGL((k_pass_tile<NP, 5, false, VEC, PR, false>), grid, block, dyn, s, p, p.Q,
+                               factor_of(w, NP, 1), dinv_of(w, NP, 1), w.partials, w.ctl, pass, final_gram, nullptr,
+                               nullptr);
+        }
     } else {
         hipLaunchKernelGGL((k_pass_tile<NP, 2, false, VEC, PR, false>), grid, block, 0, s, p, p.Q, factor_of(w, NP, pass), dinv_of(w, NP, pass),
                            w.partials, w.ctl, pass, final_gram, nullptr, nullptr);
@@ -1756,9 +1803,10 @@ hipError_t launch_pass(hipStream_t s, const Problem &p, const Work &w, int mode,
 {
     const int final_gram = (mode & 0x100) ? 1 : 0;
     mode &= 0xff;
+    if (mode == 5 && (p.np > 32 || oblique_gram || pass < 1 || pass > SCQR_MAX_PASSES)) return hipErrorInvalidValue;
     hipError_t e = hipSuccess;
     if (uses_small(p.np, oblique_gram)) {
-        prof_before(s, mode == 0 ? (fp32_gram ? "gram_f32" : "gram") : mode == 1 ? "trsm_gram" : "trsm");
+        prof_before(s, mode == 0 ? (fp32_gram ? "gram_f32" : "gram") : mode == 1 ? "trsm_gram" : mode == 5 ? "trsm_gram_mt" : "trsm");
         switch (p.np) {
         case 16: e = launch_small<16>(s, p, w, mode, pass, fp32_gram, final_gram); break;
         case 32: e = launch_small<32>(s, p, w, mode, pass, fp32_gram, final_gram); break;
@@ -1958,7 +2006,10 @@ static void launch_solve_tile(hipStream_t s, const Problem &p, const double *Rp,
     const BatchInst *ni = nullptr;
     const BatchTask *nt = nullptr;
     double *np_ = nullptr;
-    dim3 grid(pass_grid(p.m, NP)), block(512);
+    // 8 waves on 32-row panels, one workgroup per CU
+    int64_t wg = ((p.m + 31) / 32 + 7) / 8;
+    if (wg > cu_count()) wg = cu_count();
+    dim3 grid((unsigned)(wg < 1 ? 1 : wg)), block(512);
     if (vec)
         hipLaunchKernelGGL((k_pass_tile<NP, 3, false, true, kPanelRows, false>), grid, block, 0, s, p, p.Q, Rp, dinv,
                            np_, nc, 0, 0, ni, nt);

@@ -241,7 +241,9 @@ hipError_t launch_finalize_b(hipStream_t s, const BatchClass &c);
 int pass_grid(int64_t m, int np);
 int64_t pass_partial_elems(int np, bool oblique_first);
 
-// mode 0: Gram of X only; 1: Q = X R~^{-1} and Gram of Q; 2: Q = X R~^{-1} only.  Bit 0x100
+// mode 0: Gram of X only; 1: Q = X R~^{-1} and Gram of Q; 2: Q = X R~^{-1} only; 5 (n <= 32,
+// B = I): minimum traffic, Q of this pass recomputed from X through the factors of passes
+// 1 .. pass, written only by the last pass, and its Gram.  Bit 0x100
 // of mode asks for the Gram of the final pass too (final_gram option).
 // `pass` selects the predicate on the control block (0 = unconditional, -1 = FP64 redo).
 hipError_t launch_pass(hipStream_t s, const Problem &p, const Work &w, int mode, int pass,

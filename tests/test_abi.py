@@ -101,6 +101,22 @@ def test_synchronous_argument_errors(L):
     o3.shift_mode = 5
     assert L.scqr_qr(None, 5000, 30, P, 30, None, 0x900000000, 30, 0x800000000, 30,
                      0x700000000, 1 << 30, ctypes.byref(o3), info) == scqr.E_INVALID
+    # minimum-traffic passes: n <= 32 and B = I only; the flag is 0 or 1; not batched
+    o4 = scqr._Opts()
+    L.scqr_default_opts(ctypes.byref(o4))
+    assert o4.recompute == 0
+    o4.recompute = 1
+    assert L.scqr_qr(None, 5000, 33, P, 33, None, 0x900000000, 33, 0x800000000, 33,
+                     0x700000000, 1 << 30, ctypes.byref(o4), info) == scqr.E_UNSUPPORTED
+    assert L.scqr_qr(None, 5000, 30, P, 30, ctypes.byref(spd), 0x900000000, 30, 0x800000000, 30,
+                     0x700000000, 1 << 30, ctypes.byref(o4), info) == scqr.E_UNSUPPORTED
+    sz4 = ctypes.c_size_t()
+    arr = lambda v: (ctypes.c_int64 * len(v))(*v)  # noqa: E731
+    assert L.scqr_batched_workspace_bytes(1, arr([1000]), arr([8]), ctypes.byref(o4), None,
+                                          ctypes.byref(sz4)) == scqr.E_UNSUPPORTED
+    o4.recompute = 2
+    assert L.scqr_qr(None, 5000, 30, P, 30, None, 0x900000000, 30, 0x800000000, 30,
+                     0x700000000, 1 << 30, ctypes.byref(o4), info) == scqr.E_INVALID
     # backward: dX aliasing Q
     assert L.scqr_qr_backward(None, 5000, 30, P, 30, 0x800000000, 30, None, 30, None, 30, P, 30,
                               0x700000000, 1 << 30) == scqr.E_INVALID
