@@ -37,6 +37,8 @@ def lib():
         L.acc_gram_dot2.restype = None
         L.acc_gram_dot2_tridiag.argtypes = [I64, I64, P, I64, P, P, P]
         L.acc_gram_dot2_tridiag.restype = None
+        L.acc_gram_dot2_csr.argtypes = [I64, I64, P, I64, P, P, P, P]
+        L.acc_gram_dot2_csr.restype = None
         L.acc_residual.argtypes = [I64, I64, P, I64, P, I64, P, I64, ctypes.POINTER(D)]
         L.acc_residual.restype = D
         L.acc_residual_rows.argtypes = [I64, P, I64, P, I64, P, I64, P, I64, ctypes.POINTER(D)]
@@ -49,12 +51,22 @@ def _c(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def gram(Q, tridiag=None):
-    """Compensated Q^T Q, or Q^T B Q for tridiagonal B = (diag, off)."""
+def gram(Q, tridiag=None, csr=None):
+    """Compensated Q^T Q, or Q^T B Q for tridiagonal B = (diag, off) or B in compressed sparse
+    rows csr = (row_ptr, col, val)."""
     Q = _c(Q)
     m, n = Q.shape
     G = np.empty((n, n))
-    if tridiag is None:
+    if csr is not None:
+        rp = np.ascontiguousarray(csr[0], dtype=np.int64)
+        col = np.ascontiguousarray(csr[1], dtype=np.int32)
+        val = _c(csr[2])
+        if rp.size != m + 1 or rp[-1] != col.size or col.size != val.size or \
+                (col.size and (col.min() < 0 or col.max() >= m)):
+            raise ValueError("malformed compressed sparse rows")
+        lib().acc_gram_dot2_csr(m, n, Q.ctypes.data, n, rp.ctypes.data, col.ctypes.data, val.ctypes.data,
+                                G.ctypes.data)
+    elif tridiag is None:
         lib().acc_gram_dot2(m, n, Q.ctypes.data, n, G.ctypes.data)
     else:
         d, o = _c(tridiag[0]), _c(tridiag[1])
@@ -63,9 +75,9 @@ def gram(Q, tridiag=None):
     return G
 
 
-def orthogonality(Q, tridiag=None):
+def orthogonality(Q, tridiag=None, csr=None):
     """(||G - I||_2, ||G - I||_F) with G the compensated Gram."""
-    G = gram(Q, tridiag)
+    G = gram(Q, tridiag, csr)
     E = G - np.eye(G.shape[0])
     return float(np.max(np.abs(np.linalg.eigvalsh(E)))), float(np.linalg.norm(E))
 

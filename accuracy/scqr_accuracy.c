@@ -95,6 +95,31 @@ void acc_gram_dot2_tridiag(int64_t m, int64_t n, const double *Q, int64_t ldq,
     }
 }
 
+/* G = Q^T B Q for symmetric B in compressed sparse row form (row_ptr[m+1], col, val),
+ * compensated: every term q_ki * val_e * q_{col_e, j} enters one double-double sum. */
+void acc_gram_dot2_csr(int64_t m, int64_t n, const double *Q, int64_t ldq, const int64_t *row_ptr,
+                       const int32_t *col, const double *val, double *G)
+{
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t i = 0; i < n; ++i) {
+        dd *acc = (dd *)calloc((size_t)n, sizeof(dd));
+        for (int64_t k = 0; k < m; ++k) {
+            const double qi = Q[k * ldq + i];
+            for (int64_t e = row_ptr[k]; e < row_ptr[k + 1]; ++e) {
+                const double *qc = Q + (int64_t)col[e] * ldq;
+                const double b = val[e];
+                for (int64_t j = i; j < n; ++j) dot2_step3(&acc[j], qi, qc[j], b);
+            }
+        }
+        for (int64_t j = i; j < n; ++j) {
+            const double v = acc[j].hi + acc[j].lo;
+            G[i * n + j] = v;
+            G[j * n + i] = v;
+        }
+        free(acc);
+    }
+}
+
 /* Returns ||X - Q R||_F and writes ||X||_F to *xnorm.  R is n x n upper triangular
  * (only the upper triangle is read).  Each entry of Q R is a compensated dot product and the
  * squares are accumulated compensated per row, then per thread, then in thread order of

@@ -84,6 +84,8 @@ def lib():
             "orc_gram": (None, [I64, I64, P, I64, P]),
             "orc_gram_tridiag": (None, [I64, I64, P, I64, P, P, P]),
             "orc_gram_dense": (None, [I64, I64, P, I64, P, P]),
+            "orc_gram_csr": (None, [I64, I64, P, I64, P, P, P, P]),
+            "orc_gershgorin_csr": (D, [I64, P, P]),
             "orc_gram_f32": (None, [I64, I64, P, I64, I64, P]),
             "orc_gram_chunked": (None, [I64, I64, P, I64, I64, P]),
             "orc_gram_depth": (I64, [I64, I64]),
@@ -98,6 +100,8 @@ def lib():
             "orc_shift_f32": (D, [I64, I64, D]),
             "orc_scqr": (ctypes.c_int, [I64, I64, P, I64, I32, P, P, ctypes.POINTER(_Opts), P, P,
                                         ctypes.POINTER(_Info), P, P]),
+            "orc_scqr_csr": (ctypes.c_int, [I64, I64, P, I64, P, P, P, ctypes.POINTER(_Opts), P, P,
+                                            ctypes.POINTER(_Info), P, P]),
             "orc_qr_backward": (None, [I64, I64, P, P, P, P, P]),
             "orc_num_threads": (ctypes.c_int, []),
             "orc_set_num_threads": (None, [ctypes.c_int]),
@@ -148,6 +152,33 @@ def gram_dense(X, B):
     A = np.empty((n, n))
     lib().orc_gram_dense(m, n, _p(X), n, _p(B), _p(A))
     return A
+
+
+def _csr(csr, m):
+    """(row_ptr int64[m+1], col int32[nnz], val float64[nnz]) as contiguous arrays, checked."""
+    rp, col, val = _c(csr[0], np.int64), _c(csr[1], np.int32), _c(csr[2])
+    if rp.size != m + 1 or rp[0] != 0 or np.any(np.diff(rp) < 0) or rp[-1] != col.size or col.size != val.size:
+        raise ValueError("malformed compressed sparse rows")
+    if col.size and (col.min() < 0 or col.max() >= m):
+        raise ValueError("column index out of range")
+    return rp, col, val
+
+
+def gram_csr(X, csr):
+    """A = X^T B X with B = (row_ptr, col, val) in compressed sparse row form."""
+    X = _c(X)
+    m, n = X.shape
+    rp, col, val = _csr(csr, m)
+    A = np.empty((n, n))
+    lib().orc_gram_csr(m, n, _p(X), n, _p(rp), _p(col), _p(val), _p(A))
+    return A
+
+
+def gershgorin_csr(csr) -> float:
+    rp = _c(csr[0], np.int64)
+    m = rp.size - 1
+    rp, _, val = _csr(csr, m)
+    return lib().orc_gershgorin_csr(m, _p(rp), _p(val))
 
 
 def gram_f32(X, chain: int):
@@ -255,8 +286,9 @@ class Result:
 
 def scqr(X, schedule=FIXED3, shift_mode=SHIFT_PAPER, max_passes=6, B=None, tridiag=None,
          precision=0, f32_chain=None, force_breakdown_pass=0, zero_shift=False, custom_alpha=0.0,
-         bnorm=0.0, history=False, gram_chunk=0) -> Result:
-    """Run the oracle's driver; ``tridiag=(diag, off)`` or dense ``B`` select the oblique form.
+         bnorm=0.0, history=False, gram_chunk=0, csr=None) -> Result:
+    """Run the oracle's driver; ``tridiag=(diag, off)``, dense ``B`` or ``csr=(row_ptr, col,
+    val)`` select the oblique form.
     ``shift_mode=SHIFT_DEPTH`` sums every Gram in chunks of ``gram_chunk`` rows and shifts with
     the depth of that summation (Euclidean inner product only)."""
     X = _c(X)
@@ -280,8 +312,13 @@ def scqr(X, schedule=FIXED3, shift_mode=SHIFT_PAPER, max_passes=6, B=None, tridi
     hp = 16 if history else 0
     gh = np.zeros((hp, n, n)) if history else None
     rh = np.zeros((hp, n, n)) if history else None
-    lib().orc_scqr(m, n, _p(X), n, kind, _p(b0), _p(b1), ctypes.byref(o), _p(Q), _p(R),
-                   ctypes.byref(info), _p(gh), _p(rh))
+    if csr is not None:
+        rp, col, val = _csr(csr, m)
+        lib().orc_scqr_csr(m, n, _p(X), n, _p(rp), _p(col), _p(val), ctypes.byref(o), _p(Q), _p(R),
+                           ctypes.byref(info), _p(gh), _p(rh))
+    else:
+        lib().orc_scqr(m, n, _p(X), n, kind, _p(b0), _p(b1), ctypes.byref(o), _p(Q), _p(R),
+                       ctypes.byref(info), _p(gh), _p(rh))
     p = info.passes
     k = max(p + (1 if info.status == BREAKDOWN else 0), 1)
     res = Result(Q, R, info.status, p, info.shifted_mask, info.breakdown_mask, info.fell_back,

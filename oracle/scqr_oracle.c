@@ -34,7 +34,7 @@
 enum { ORC_OK = 0, ORC_BREAKDOWN = 5, ORC_NOT_CONVERGED = 6, ORC_NONFINITE = 7, ORC_INVALID = 1 };
 enum { ORC_FIXED3 = 0, ORC_ADAPTIVE = 1, ORC_CHOLQR2 = 2, ORC_ITERATED = 3 };
 enum { ORC_SHIFT_PAPER = 0, ORC_SHIFT_FRO = 1, ORC_SHIFT_SMALL = 2, ORC_SHIFT_CUSTOM = 3, ORC_SHIFT_DEPTH = 4 };
-enum { ORC_B_NONE = 0, ORC_B_TRIDIAG = 1, ORC_B_DENSE = 2 };
+enum { ORC_B_NONE = 0, ORC_B_TRIDIAG = 1, ORC_B_DENSE = 2, ORC_B_CSR = 3 };
 
 /* ------------------------------------------------------------------------------------------
  * Gram matrices (equation (eq:gram); oblique form X^T B X of Section 5, Algorithm 4).
@@ -135,6 +135,37 @@ void orc_gram_tridiag(int64_t m, int64_t n, const double *X, int64_t ldx, const 
 {
     tri_ctx c = {diag, off};
     gram_driver(m, n, X, ldx, tri_row, &c, A);
+}
+
+/* General sparse symmetric B in compressed sparse row form (the storage of the sparse B of
+ * Section 7): (B x)_k is the sum over the stored entries e of row k, in storage order, of
+ * val_e x_{col_e}, added left to right from zero. */
+typedef struct {
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const double *val;
+} csr_ctx;
+
+static void csr_row(int64_t k, int64_t n, const double *X, int64_t ldx, int64_t m, const void *vctx,
+                    double *y)
+{
+    const csr_ctx *c = (const csr_ctx *)vctx;
+    (void)m;
+    for (int64_t j = 0; j < n; ++j) y[j] = 0.0;
+    for (int64_t e = c->row_ptr[k]; e < c->row_ptr[k + 1]; ++e) {
+        const double b = c->val[e];
+        const double *xr = X + (int64_t)c->col[e] * ldx;
+        for (int64_t j = 0; j < n; ++j) y[j] = y[j] + b * xr[j];
+    }
+}
+
+/* A = X^T B X with B in compressed sparse row form (Section 7, oblique inner product; the
+ * row-by-row product Y = B X followed by X^T Y, without storing Y). */
+void orc_gram_csr(int64_t m, int64_t n, const double *X, int64_t ldx, const int64_t *row_ptr,
+                  const int32_t *col, const double *val, double *A)
+{
+    csr_ctx c = {row_ptr, col, val};
+    gram_driver(m, n, X, ldx, csr_row, &c, A);
 }
 
 /* A = X^T B X with dense B (m x m row-major): Y = B X by plain loops, then X^T Y. */
@@ -370,6 +401,19 @@ double orc_gershgorin_tridiag(int64_t m, const double *diag, const double *off)
     return best;
 }
 
+/* ||B||_2 bound for B in compressed sparse row form: the largest absolute row sum, each row
+ * summed in storage order (Gershgorin, as for the tridiagonal B). */
+double orc_gershgorin_csr(int64_t m, const int64_t *row_ptr, const double *val)
+{
+    double best = 0.0;
+    for (int64_t k = 0; k < m; ++k) {
+        double v = 0.0;
+        for (int64_t e = row_ptr[k]; e < row_ptr[k + 1]; ++e) v = v + fabs(val[e]);
+        if (v > best) best = v;
+    }
+    return best;
+}
+
 /* Shift of the first pass.
  *   Euclidean, equation (eq:finds2):  s = 11 (m n + n (n+1)) u ||X||_2^2
  *   Oblique,   equation (eq:finds2B): s = 11 (2 m sqrt(m n) + n (n+1)) u ||X||_2^2 ||B||_2
@@ -463,11 +507,22 @@ static double dev_from_identity(int64_t n, const double *A)
     return sqrt(s);
 }
 
-/* B descriptor: kind 0 none, 1 tridiagonal (diag[m], off[m-1]), 2 dense (m x m). */
-int orc_scqr(int64_t m, int64_t n, const double *X, int64_t ldx, int32_t bkind,
-             const double *b0, const double *b1, const orc_opts *opt, double *Q, double *R,
-             orc_info *info, double *gram_hist, double *rt_hist)
+/* B descriptor: kind 0 none, 1 tridiagonal (diag[m], off[m-1]), 2 dense (m x m), 3 compressed
+ * sparse rows (row_ptr[m+1], col[nnz], val[nnz]). */
+typedef struct {
+    int32_t kind;
+    const double *b0, *b1;
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const double *val;
+} bop_t;
+
+static int scqr_run(int64_t m, int64_t n, const double *X, int64_t ldx, const bop_t *bop,
+                    const orc_opts *opt, double *Q, double *R, orc_info *info, double *gram_hist,
+                    double *rt_hist)
 {
+    const int32_t bkind = bop->kind;
+    const double *b0 = bop->b0, *b1 = bop->b1;
     memset(info, 0, sizeof(*info));
     const int depth_mode = opt->shift_mode == ORC_SHIFT_DEPTH;
     if (m < n || n < 1 || ldx < n || opt->max_passes < 1 || opt->max_passes > 16 ||
@@ -486,6 +541,8 @@ int orc_scqr(int64_t m, int64_t n, const double *X, int64_t ldx, int32_t bkind,
             bnorm = opt->bnorm;
         else if (bkind == ORC_B_TRIDIAG)
             bnorm = orc_gershgorin_tridiag(m, b0, b1);
+        else if (bkind == ORC_B_CSR)
+            bnorm = orc_gershgorin_csr(m, bop->row_ptr, bop->val);
         else {
             double *w = (double *)malloc(sizeof(double) * (size_t)(m));
             orc_sym_eig(m, b0, w);
@@ -520,6 +577,8 @@ int orc_scqr(int64_t m, int64_t n, const double *X, int64_t ldx, int32_t bkind,
             orc_gram_tridiag(m, n, Q, n, b0, b1, A);
         else if (bkind == ORC_B_DENSE)
             orc_gram_dense(m, n, Q, n, b0, A);
+        else if (bkind == ORC_B_CSR)
+            orc_gram_csr(m, n, Q, n, bop->row_ptr, bop->col, bop->val, A);
         else if (depth_mode)
             orc_gram_chunked(m, n, Q, n, opt->gram_chunk, A);
         else
@@ -634,6 +693,28 @@ int orc_scqr(int64_t m, int64_t n, const double *X, int64_t ldx, int32_t bkind,
     free(Ae);
     free(A);
     return status;
+}
+
+int orc_scqr(int64_t m, int64_t n, const double *X, int64_t ldx, int32_t bkind, const double *b0,
+             const double *b1, const orc_opts *opt, double *Q, double *R, orc_info *info,
+             double *gram_hist, double *rt_hist)
+{
+    if (bkind == ORC_B_CSR) {
+        memset(info, 0, sizeof(*info));
+        info->status = ORC_INVALID;
+        return ORC_INVALID;
+    }
+    const bop_t b = {bkind, b0, b1, NULL, NULL, NULL};
+    return scqr_run(m, n, X, ldx, &b, opt, Q, R, info, gram_hist, rt_hist);
+}
+
+/* The driver with B in compressed sparse row form (Section 7). */
+int orc_scqr_csr(int64_t m, int64_t n, const double *X, int64_t ldx, const int64_t *row_ptr,
+                 const int32_t *col, const double *val, const orc_opts *opt, double *Q, double *R,
+                 orc_info *info, double *gram_hist, double *rt_hist)
+{
+    const bop_t b = {ORC_B_CSR, NULL, NULL, row_ptr, col, val};
+    return scqr_run(m, n, X, ldx, &b, opt, Q, R, info, gram_hist, rt_hist);
 }
 
 /* ------------------------------------------------------------------------------------------

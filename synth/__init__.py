@@ -11,6 +11,12 @@ builds test matrices in the way the paper's numerical experiments describe them:
   matrices of Section 7, which are not available).
 * ``dense_spd_b``: a dense SPD B = W diag(lambda) W^T with geometric spectrum (Section 6,
   Table 3 construction, B built "as in (testmat)").
+* ``stencil_b`` / ``random_pattern_b``: general sparse SPD B in CSR (row pointers, column
+  indices, values) with the sparsity of the SuiteSparse matrices of Section 7 (Table of test
+  matrices: about 4 to 48 nonzeros per row): a 2-D 5-point or 3-D 27-point stencil pattern, or
+  a random symmetric pattern within a band.  Off-diagonal entries are -u_ij, u_ij uniform in
+  [0.1, 1] and symmetric; the diagonal is the row's absolute off-diagonal sum plus d_i with
+  log10(d_i) uniform in [-3, 3], so B is strictly diagonally dominant, hence SPD.
 * ``batch_spec``: shapes and condition numbers for a batch of independent problems.
 * ``upstream_grads``: dQ ~ N(0,1), dR = triu(N(0,1)) for the QR adjoint.
 
@@ -134,6 +140,96 @@ def dense_spd_b(m: int, kappa_b: float, seed: int) -> np.ndarray:
     lam = singular_values(m, kappa_b)
     b = (w * lam) @ w.T
     return 0.5 * (b + b.T)
+
+
+@dataclass(frozen=True)
+class CsrB:
+    """Symmetric sparse B in compressed sparse row form: row i holds columns
+    col[row_ptr[i]:row_ptr[i+1]] (ascending) with values val[...]."""
+    row_ptr: np.ndarray  # int64, m + 1
+    col: np.ndarray      # int32, nnz
+    val: np.ndarray      # float64, nnz
+
+    @property
+    def m(self) -> int:
+        return len(self.row_ptr) - 1
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    def dense(self) -> np.ndarray:
+        """The m x m matrix (small m only)."""
+        b = np.zeros((self.m, self.m))
+        rows = np.repeat(np.arange(self.m), np.diff(self.row_ptr))
+        b[rows, self.col] = self.val
+        return b
+
+
+def _spd_from_pairs(m: int, i: np.ndarray, j: np.ndarray, rng) -> CsrB:
+    """CSR of the symmetric B with off-diagonal entries (i, j), (j, i) for the given pairs
+    (i < j, no repeats): -u_ij, u_ij ~ U(0.1, 1), and a dominant diagonal."""
+    u = rng.uniform(0.1, 1.0, size=len(i))
+    d = np.power(10.0, rng.uniform(-3.0, 3.0, size=m))
+    rows = np.concatenate([i, j, np.arange(m)])
+    cols = np.concatenate([j, i, np.arange(m)])
+    absum = np.bincount(i, weights=u, minlength=m) + np.bincount(j, weights=u, minlength=m)
+    vals = np.concatenate([-u, -u, absum + d])
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=m), out=row_ptr[1:])
+    return CsrB(row_ptr, cols.astype(np.int32), np.ascontiguousarray(vals, dtype=np.float64))
+
+
+def stencil_b(m: int, kind: str, seed: int) -> CsrB:
+    """SPD B in CSR with a finite-difference stencil pattern on a grid of m points numbered
+    row by row: '5pt' on a g x ceil(m/g) grid (g = ceil(sqrt m); up to 5 nonzeros per row, like
+    apache2, G3_circuit or parabolic_fem), '27pt' on a g x g x ceil(m/g^2) grid (g = ceil(m^(1/3));
+    up to 27 per row, like shipsec8 or watercube)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), 17])))
+    idx = np.arange(m, dtype=np.int64)
+    if kind == "5pt":
+        g = int(np.ceil(np.sqrt(m)))
+        coords = [idx % g, idx // g]
+        steps = [(1, 0), (0, 1)]
+        strides = [1, g]
+    elif kind == "27pt":
+        g = int(np.ceil(m ** (1.0 / 3.0)))
+        coords = [idx % g, (idx // g) % g, idx // (g * g)]
+        steps = [(a, b, c) for c in (-1, 0, 1) for b in (-1, 0, 1) for a in (-1, 0, 1)]
+        # half of the neighbours: those with a positive linear offset
+        steps = [st for st in steps if st[0] + g * st[1] + g * g * st[2] > 0]
+        strides = [1, g, g * g]
+    else:
+        raise ValueError(kind)
+    ii, jj = [], []
+    for st in steps:
+        off = sum(a * s for a, s in zip(st, strides))
+        # a neighbour exists when every coordinate stays on the grid; the last (slowest)
+        # coordinate is bounded by the number of points, checked through idx + off < m
+        ok = idx + off < m
+        for dim, (c, a) in enumerate(zip(coords, st)):
+            if a == 1 and dim < len(coords) - 1:
+                ok &= c < g - 1
+            elif a == -1:
+                ok &= c > 0
+        ii.append(idx[ok])
+        jj.append(idx[ok] + off)
+    return _spd_from_pairs(m, np.concatenate(ii), np.concatenate(jj), rng)
+
+
+def random_pattern_b(m: int, per_row: int, window: int, seed: int) -> CsrB:
+    """SPD B in CSR with a random symmetric pattern: row i is coupled to (per_row - 1) / 2 rows
+    i + o, o uniform in [1, window] (repeats and pairs past the end dropped), and by symmetry
+    to as many below; about per_row nonzeros per row (like bone010, Geo_1438 or serena at 48)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), 19])))
+    h = max(0, (per_row - 1) // 2)
+    i = np.repeat(np.arange(m, dtype=np.int64), h)
+    j = i + rng.integers(1, window + 1, size=len(i))
+    keep = j < m
+    key = np.unique(i[keep] * m + j[keep])
+    return _spd_from_pairs(m, key // m, key % m, rng)
 
 
 @dataclass(frozen=True)

@@ -119,3 +119,40 @@ def test_tridiagonal_dot2_keeps_cancelled_low_part():
     Q = np.array([[1.0, 1.0], [2.0 ** -27, 2.0 ** -27], [1.0, -1.0]])
     assert accuracy.gram(Q, (np.ones(3), np.zeros(2)))[0, 1] == 2.0 ** -54
     assert accuracy.gram(Q, (np.array([1.0, 4.0, 1.0]), np.zeros(2)))[0, 1] == 2.0 ** -52
+
+
+def _csr_of_dense(D):
+    m = D.shape[0]
+    rows, cols = np.nonzero(D)
+    rp = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=m), out=rp[1:])
+    return rp, cols.astype(np.int32), D[rows, cols]
+
+
+def test_csr_dot2_gram_exact_on_integers_and_cancellation():
+    rng = np.random.default_rng(6)
+    m, n = 150, 5
+    Q = rng.integers(-40, 41, size=(m, n)).astype(np.float64)
+    Bi = rng.integers(-3, 4, size=(m, m)) * (rng.random((m, m)) < 0.05)
+    Bi = np.triu(Bi, 1) + np.triu(Bi, 1).T + np.diag(rng.integers(5, 9, size=m))
+    G = accuracy.gram(Q, csr=_csr_of_dense(Bi.astype(np.float64)))
+    want = Q.astype(np.int64).T @ (Bi @ Q.astype(np.int64))
+    assert np.array_equal(G, want.astype(np.float64))
+    # the cancellation of the tridiagonal pin, through CSR: B = diag(1, 4, 1)
+    Q3 = np.array([[1.0, 1.0], [2.0 ** -27, 2.0 ** -27], [1.0, -1.0]])
+    assert accuracy.gram(Q3, csr=_csr_of_dense(np.diag([1.0, 4.0, 1.0])))[0, 1] == 2.0 ** -52
+
+
+def test_csr_dot2_gram_matches_tridiagonal():
+    rng = np.random.default_rng(7)
+    m, n = 500, 4
+    Q = rng.standard_normal((m, n))
+    d = 2.0 + rng.random(m)
+    o = -rng.random(m - 1)
+    Bm = np.diag(d) + np.diag(o, 1) + np.diag(o, -1)
+    Gc = accuracy.gram(Q, csr=_csr_of_dense(Bm))
+    Gt = accuracy.gram(Q, (d, o))
+    # both compensated sums are accurate to about u^2 relative to |Q|^T |B| |Q|: equal up to
+    # the final rounding
+    scale = np.abs(Q).T @ np.abs(Bm) @ np.abs(Q)
+    assert np.all(np.abs(Gc - Gt) <= 2.0 ** -52 * scale)

@@ -66,3 +66,50 @@ def test_upstream_grads():
     assert dq.shape == (100, 7) and dr.shape == (7, 7)
     assert np.all(np.tril(dr, -1) == 0)
     assert abs(np.std(dq) - 1) < 0.1
+
+
+def _grid_neighbours(kind, m, i):
+    """Neighbours of grid point i written out from the stencil's definition."""
+    if kind == "5pt":
+        g = int(np.ceil(np.sqrt(m)))
+        return {j for j in (i - 1, i + 1, i - g, i + g) if 0 <= j < m and (abs(j - i) != 1 or j // g == i // g)}
+    g = int(np.ceil(m ** (1.0 / 3.0)))
+    x, y, z = i % g, (i // g) % g, i // (g * g)
+    out = set()
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                X, Y, Z = x + dx, y + dy, z + dz
+                if (dx, dy, dz) != (0, 0, 0) and 0 <= X < g and 0 <= Y < g and Z >= 0 and X + g * Y + g * g * Z < m:
+                    out.add(X + g * Y + g * g * Z)
+    return out
+
+
+@pytest.mark.parametrize("kind,m", [("5pt", 37), ("5pt", 1000), ("27pt", 37), ("27pt", 1000)])
+def test_stencil_b_pattern_and_spd(kind, m):
+    B = synth.stencil_b(m, kind, seed=5)
+    assert B.row_ptr.dtype == np.int64 and B.col.dtype == np.int32 and B.val.dtype == np.float64
+    assert B.row_ptr[0] == 0 and B.nnz == len(B.col) == len(B.val)
+    for i in range(m):
+        cols = B.col[B.row_ptr[i]:B.row_ptr[i + 1]]
+        assert np.all(np.diff(cols) > 0)  # ascending, no repeats
+        assert set(cols.tolist()) - {i} == _grid_neighbours(kind, m, i)
+    D = B.dense()
+    np.testing.assert_array_equal(D, D.T)
+    off = D - np.diag(np.diag(D))
+    assert np.all(np.diag(D) - np.abs(off).sum(axis=1) >= 1e-3 * (1 - 1e-12))  # dominant diagonal
+    assert np.linalg.eigvalsh(D)[0] > 0
+    assert synth.stencil_b(m, kind, seed=5).val.tobytes() == B.val.tobytes()
+
+
+def test_random_pattern_b():
+    m = 3000
+    B = synth.random_pattern_b(m, 48, 200, seed=6)
+    D = B.dense()
+    np.testing.assert_array_equal(D, D.T)
+    assert np.linalg.eigvalsh(D)[0] > 0
+    rows = np.repeat(np.arange(m), np.diff(B.row_ptr))
+    assert np.all(np.abs(B.col - rows) <= 200)
+    assert 40 <= B.nnz / m <= 48
+    for i in range(0, m, 97):
+        assert np.all(np.diff(B.col[B.row_ptr[i]:B.row_ptr[i + 1]]) > 0)
