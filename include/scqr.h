@@ -130,14 +130,27 @@ typedef struct {
 } scqr_info;
 
 /* Optional SPD operator B of the oblique inner product (Section 5).  NULL or kind NONE means
- * B = I.  TRIDIAG: B symmetric tridiagonal with diag[m] and off[m-1] (device pointers); the
- * caller guarantees B is SPD. */
-enum { SCQR_B_NONE = 0, SCQR_B_TRIDIAG = 1 };
+ * B = I.  The caller guarantees that B is symmetric positive definite.
+ *   TRIDIAG: B symmetric tridiagonal with diag[m] and off[m-1] (device pointers).
+ *   CSR: general sparse B in compressed sparse row form, the storage of the sparse B of
+ *        Section 7 (device pointers): the entries of row i are col[e], val[e] for
+ *        e = row_ptr[i] .. row_ptr[i+1]-1, row_ptr has m + 1 entries with row_ptr[0] = 0 and
+ *        row_ptr[m] = nnz, both triangles are stored, the order inside a row is free.  (B x)_i
+ *        is summed in storage order.  The indices live on the device and are checked by the
+ *        kernels that read them: an entry whose row pointers leave [0, nnz] or decrease, or
+ *        whose column leaves [0, m), is skipped, and scqr_qr reports SCQR_E_INVALID in info
+ *        (scqr_gram has no status record: the Gram then lacks those entries).  The shift's
+ *        ||B||_2 bound is the largest absolute row sum (Gershgorin) unless opts.bnorm > 0. */
+enum { SCQR_B_NONE = 0, SCQR_B_TRIDIAG = 1, SCQR_B_CSR = 2 };
 typedef struct {
     int32_t kind;
     int32_t reserved;
-    const double *diag;
-    const double *off;
+    const double *diag;      /* TRIDIAG */
+    const double *off;       /* TRIDIAG */
+    const int64_t *row_ptr;  /* CSR */
+    const int32_t *col;      /* CSR */
+    const double *val;       /* CSR */
+    int64_t nnz;             /* CSR: number of stored entries (row_ptr[m]) */
 } scqr_spd_op;
 
 /* Fills *opts with the defaults listed above. */
@@ -159,8 +172,8 @@ scqr_status scqr_workspace_bytes(int64_t m, int64_t n, const scqr_spd_op *B,
  *       triangle is written with zeros.  Must not alias X, Q or the workspace.
  *   ws  workspace of at least scqr_workspace_bytes() bytes, 256-byte aligned.
  *   info device pointer to one scqr_info, written on the stream.
- * With B of kind TRIDIAG, Q^T B Q = I instead of Q^T Q = I (Algorithm 5; passes 2 and later
- * use the B-Gram Q^T B Q).
+ * With B of kind TRIDIAG or CSR, Q^T B Q = I instead of Q^T Q = I (Algorithm 5; passes 2 and
+ * later use the B-Gram Q^T B Q).
  */
 scqr_status scqr_qr(void *stream, int64_t m, int64_t n, const double *X, int64_t ldx,
                     const scqr_spd_op *B, double *Q, int64_t ldq, double *R, int64_t ldr,
@@ -187,8 +200,8 @@ scqr_status scqr_qr_noalloc(void *stream, int64_t m, int64_t n, const double *X,
                             const scqr_opts *opts, scqr_info *info);
 
 /*
- * Gram matrix G = X^T X (equation (eq:gram)), or X^T B X for tridiagonal B (Algorithm 4 line
- * 1): the split-m SYRK of one pass with a fixed-order reduction across workgroups.  G is
+ * Gram matrix G = X^T X (equation (eq:gram)), or X^T B X for tridiagonal or CSR B (Algorithm 4
+ * line 1): the split-m SYRK of one pass with a fixed-order reduction across workgroups.  G is
  * n x n, ldg >= n, both triangles written (the upper triangle mirrored).
  */
 scqr_status scqr_gram(void *stream, int64_t m, int64_t n, const double *X, int64_t ldx,

@@ -7,7 +7,8 @@ library has not been built (``python -m paper_1809_11085_amd.build``).
 
 Functions mirror the C entry points:
 
-* ``qr(X, B=None, **opts) -> (Q, R, info)``  Algorithms 1-3 and 5 of Fukaya et al.
+* ``qr(X, B=None, **opts) -> (Q, R, info)``  Algorithms 1-3 and 5 of Fukaya et al.; B is a
+  tridiagonal ``(diag, off)`` or a ``CsrB(row_ptr, col, val)`` in compressed sparse rows
 * ``gram(X, B=None) -> G``                   A = X^T X (or X^T B X), equation (eq:gram)
 * ``trsm(X, R) -> Q``                        Q = X R^{-1} row by row (Algorithm 1 line 4)
 * ``qr_batched(Xs, **opts)``                 independent problems
@@ -19,6 +20,7 @@ from __future__ import annotations
 import ctypes
 import os
 from dataclasses import dataclass
+from typing import NamedTuple
 
 import torch
 
@@ -80,7 +82,17 @@ class _Info(ctypes.Structure):
 
 class _SpdOp(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("diag", ctypes.c_void_p), ("off", ctypes.c_void_p)]
+                ("diag", ctypes.c_void_p), ("off", ctypes.c_void_p),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("nnz", ctypes.c_int64)]
+
+
+class CsrB(NamedTuple):
+    """A sparse symmetric positive definite B in compressed sparse rows on the device:
+    row_ptr int64 [m + 1], col int32 [nnz], val float64 [nnz] (CUDA tensors, contiguous)."""
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
 
 
 class _KernelStat(ctypes.Structure):
@@ -203,6 +215,20 @@ def _opts(schedule="adaptive", shift="paper", precision="fp64", max_passes=6, fi
 def _spd(B, m: int):
     if B is None:
         return None
+    if isinstance(B, CsrB):
+        for t, nm, dt in ((B.row_ptr, "row_ptr", torch.int64), (B.col, "col", torch.int32),
+                          (B.val, "val", torch.float64)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.dim() != 1:
+                raise TypeError(f"CSR {nm} must be a contiguous 1-D {dt} CUDA tensor")
+        if B.row_ptr.numel() != m + 1 or B.col.numel() != B.val.numel():
+            raise ValueError("CSR B needs row_ptr[m + 1] and col, val of equal length")
+        op = _SpdOp()
+        op.kind = 2
+        op.row_ptr = B.row_ptr.data_ptr()
+        op.col = B.col.data_ptr() if B.col.numel() else B.row_ptr.data_ptr()
+        op.val = B.val.data_ptr() if B.val.numel() else B.row_ptr.data_ptr()
+        op.nnz = B.val.numel()
+        return op
     diag, off = B
     for t, nm in ((diag, "B diag"), (off, "B off")):
         if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
@@ -288,7 +314,8 @@ def qr(X: torch.Tensor, B=None, *, inplace=False, check=True, trace=False, **opt
     ``info`` and raises ScqrError when the factorization failed numerically (breakdown,
     max_passes reached, non-finite Gram); "status" decodes without raising, so that the caller
     inspects ``info.status``; False returns the raw device record without synchronizing.
-    ``B = (diag, off)`` selects the oblique inner product with a tridiagonal SPD B.
+    ``B = (diag, off)`` selects the oblique inner product with a tridiagonal SPD B, ``B = CsrB(row_ptr,
+    col, val)`` with a sparse SPD B in compressed sparse rows.
     ``trace=True`` also returns per-pass input Grams and triangular factors in ``info.trace``
     (shape [passes, 2, n, n]).  ``recompute=True`` (n <= 32, B = I) selects the minimum-traffic
     passes: each pass before the last recomputes its input from X instead of reading a stored

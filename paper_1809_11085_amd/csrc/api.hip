@@ -155,14 +155,36 @@ Work carve(void *ws, const Layout &L)
     return w;
 }
 
-bool is_oblique(const scqr_spd_op *B) { return B && B->kind == SCQR_B_TRIDIAG; }
+bool is_oblique(const scqr_spd_op *B) { return B && (B->kind == SCQR_B_TRIDIAG || B->kind == SCQR_B_CSR); }
 
 scqr_status check_B(const scqr_spd_op *B, int64_t m)
 {
     if (!B || B->kind == SCQR_B_NONE) return SCQR_OK;
-    if (B->kind != SCQR_B_TRIDIAG) return SCQR_E_INVALID;
-    if (!B->diag || (m > 1 && !B->off)) return SCQR_E_INVALID;
+    if (B->kind == SCQR_B_TRIDIAG) {
+        if (!B->diag || (m > 1 && !B->off)) return SCQR_E_INVALID;
+        return SCQR_OK;
+    }
+    if (B->kind != SCQR_B_CSR) return SCQR_E_INVALID;
+    if (!B->row_ptr || B->nnz < 0 || (B->nnz > 0 && (!B->col || !B->val))) return SCQR_E_INVALID;
+    if (m > (int64_t)INT32_MAX) return SCQR_E_UNSUPPORTED;  // 32-bit column indices
     return SCQR_OK;
+}
+
+// The operator B of the oblique Gram kernels (tridiagonal or CSR); index errors of a CSR B
+// are flagged in the control block.
+void set_b(Problem &p, const scqr_spd_op *B, Ctl *ctl)
+{
+    if (!is_oblique(B)) return;
+    if (B->kind == SCQR_B_TRIDIAG) {
+        p.bdiag = B->diag;
+        p.boff = B->off;
+        return;
+    }
+    p.brp = B->row_ptr;
+    p.bcol = B->col;
+    p.bval = B->val;
+    p.bnnz = B->nnz;
+    p.bad_b = &ctl->bad_b;
 }
 
 scqr_status hip_status(hipError_t e) { return e == hipSuccess ? SCQR_OK : SCQR_E_HIP; }
@@ -607,8 +629,7 @@ scqr_status qr_enqueue(void *stream, int64_t m, int64_t n, const double *X, int6
     p.ldq = ldq;
     p.R = R;
     p.ldr = ldr;
-    p.bdiag = obl ? B->diag : nullptr;
-    p.boff = obl ? B->off : nullptr;
+    set_b(p, B, w.ctl);
     p.gram_depth = gram_depth_single(m, L.nwg, L.nlvl2);
     SchedParams sp;
     sp.schedule = o.schedule;
@@ -729,8 +750,7 @@ scqr_status scqr_gram(void *stream, int64_t m, int64_t n, const double *X, int64
     p.np = L.np;
     p.X = X;
     p.ldx = ldx;
-    p.bdiag = obl ? B->diag : nullptr;
-    p.boff = obl ? B->off : nullptr;
+    set_b(p, B, w.ctl);
     const int64_t E = pass_partial_elems(L.np, false);
     SchedParams sp{};
     hipError_t e = launch_init(s, p, w, sp);

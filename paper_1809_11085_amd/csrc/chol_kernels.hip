@@ -578,6 +578,16 @@ __device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const
             if (!(c_active && c_pass == pass - 1 && c_last == 0)) return;
         }
     }
+    if (ctl->bad_b) {
+        // the Gram kernel skipped out-of-range indices of the caller's CSR B
+        if (threadIdx.x == 0) {
+            ctl->active = 0;
+            ctl->status = SCQR_E_INVALID;
+            sp.info->status = SCQR_E_INVALID;
+            sp.info->passes = pass - 1;
+        }
+        return;
+    }
     const int n = p.n;
     const bool oblique = sp.oblique != 0;
     const bool f32pass = (variant == 0 && pass == 1 && sp.precision == SCQR_PREC_FP32_FIRST);
@@ -789,6 +799,7 @@ __device__ __forceinline__ void init_body(Ctl *ctl, scqr_info *info)
         ctl->redo_fp64 = 0;
         ctl->status = SCQR_E_NOT_CONVERGED;
         ctl->f32_pass = 0;
+        ctl->bad_b = 0;
         ctl->bnorm = 1.0;
     }
     if (info) {

@@ -1474,6 +1474,155 @@ k_gram_lds(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
                                             bmax + blockIdx.x, ctl, pass, final_gram, p0, p1);
 }
 
+// ------------------------------------------------------------------------------------------
+// Oblique Gram X^T B X for a general sparse B in compressed sparse rows (Section 7).  A
+// workgroup takes a contiguous share of 16-row panels.  For each panel it stages the rows of X
+// in LDS and forms the matching rows of Y = B X beside them: thread (r, c) sums, in storage
+// order, val_e x_{col_e, c} over the entries e of row r, the rows x_{col_e} gathered from HBM
+// (through L2) and read coalesced by the NP threads of the row, eight entries' loads issued
+// before their products are added.  The upper tiles of X^T Y then accumulate on FP64 MFMA as in
+// the tridiagonal kernels.  Y never reaches HBM: the blocked strategy of Section 7 with blocks
+// of 16 rows of Y (all n columns) instead of column blocks.
+//   EUC (first pass): also X^T X for ||X||_2 of (eq:finds2B) and the Gershgorin bound (largest
+//   absolute row sum, each row summed in storage order) of the workgroup's rows into bmax.
+// Row pointers outside [0, nnz] or decreasing, and columns outside [0, m), are never used as
+// addresses: the entry is skipped and *p.bad_b set.
+template <int NP, int WAVES, bool EUC>
+__global__ void __launch_bounds__(WAVES * 64)
+k_gram_csr(Problem p, double *__restrict__ partials, double *__restrict__ bmax, const Ctl *__restrict__ ctl,
+           int pass, int final_gram)
+{
+    constexpr int NT = NP / 16;
+    constexpr int T = NT * (NT + 1) / 2;
+    constexpr int TPW = (T + WAVES - 1) / WAVES;
+    constexpr int PR = 16;
+    constexpr int S = NP + 1;
+    constexpr int NTHR = WAVES * 64;
+    constexpr int RPS = NTHR / NP;  // rows of Y formed per step
+    constexpr int GB = NP >= 256 ? 4 : 8;  // entries whose loads are issued together
+    static_assert(NTHR % NP == 0 && RPS >= 1 && PR % RPS == 0, "Y rows split evenly over the threads");
+    __shared__ double xs[PR * S], ys[PR * S];
+    __shared__ double gmax[NTHR];
+
+    if (!gate(ctl, pass)) return;
+    if (!gram_needed(ctl, pass, final_gram)) return;
+
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int n = p.n;
+    const int64_t m = p.m;
+    const int c = threadIdx.x % NP, rs = threadIdx.x / NP;
+    const int64_t npanels = (m + PR - 1) / PR;
+    const int64_t per = (npanels + gridDim.x - 1) / gridDim.x;
+    const int64_t p0 = (int64_t)blockIdx.x * per;
+    const int64_t p1 = (p0 + per < npanels) ? p0 + per : npanels;
+
+    d4 acc[TPW], acce[EUC ? TPW : 1];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) acc[u] = (d4){0.0, 0.0, 0.0, 0.0};
+    if (EUC) {
+#pragma unroll
+        for (int u = 0; u < (EUC ? TPW : 1); ++u) acce[u] = (d4){0.0, 0.0, 0.0, 0.0};
+    }
+    int ti[TPW], tj[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int t = wv + u * WAVES < T ? wv + u * WAVES : 0;
+        ti[u] = 16 * tile_row(NT, t);
+        tj[u] = 16 * tile_col(NT, t);
+    }
+    bool bad = false;
+    double bm = 0.0;
+
+    for (int64_t pn = p0; pn < p1; ++pn) {
+        const int64_t r0 = pn * PR;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < PR * NP; idx += NTHR) {
+            const int rr = idx / NP, cc = idx % NP;
+            const int64_t row = r0 + rr;
+            xs[rr * S + cc] = (row < m && cc < n) ? as_global(p.X)[row * p.ldx + cc] : 0.0;
+        }
+        for (int rr = rs; rr < PR; rr += RPS) {
+            const int64_t row = r0 + rr;
+            double y = 0.0, asum = 0.0;
+            if (row < m) {
+                int64_t e0 = as_global(p.brp)[row], e1 = as_global(p.brp)[row + 1];
+                if (!(e0 >= 0 && e0 <= e1 && e1 <= p.bnnz)) {
+                    bad = true;
+                    e1 = e0;
+                }
+                for (int64_t e = e0; e < e1; e += GB) {
+                    int32_t js[GB];
+                    double vs[GB], xv[GB];
+#pragma unroll
+                    for (int u = 0; u < GB; ++u) {
+                        js[u] = -1;
+                        vs[u] = 0.0;
+                        if (e + u < e1) {
+                            const int32_t j = as_global(p.bcol)[e + u];
+                            vs[u] = as_global(p.bval)[e + u];
+                            if (j >= 0 && (int64_t)j < m)
+                                js[u] = j;
+                            else
+                                bad = true;
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < GB; ++u)
+                        xv[u] = (js[u] >= 0 && c < n) ? as_global(p.X)[(int64_t)js[u] * p.ldx + c] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < GB; ++u) {
+                        if (js[u] >= 0) {
+                            y = __builtin_fma(vs[u], xv[u], y);
+                            if (EUC) asum += fabs(vs[u]);
+                        }
+                    }
+                }
+            }
+            ys[rr * S + c] = y;
+            if (EUC && c == 0) bm = asum > bm ? asum : bm;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s4 = 0; s4 < PR / 4; ++s4) {
+            const int rr = 4 * s4 + (lane >> 4);
+            const double *xrow = xs + rr * S + (lane & 15);
+            const double *yrow = ys + rr * S + (lane & 15);
+#pragma unroll
+            for (int u = 0; u < TPW; ++u) {
+                if (wv + u * WAVES < T) {
+                    const double a = xrow[ti[u]];
+                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, yrow[tj[u]], acc[u], 0, 0, 0);
+                    if (EUC) acce[EUC ? u : 0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xrow[tj[u]], acce[EUC ? u : 0], 0, 0, 0);
+                }
+            }
+        }
+    }
+    if (bad) *p.bad_b = 1;
+    constexpr int64_t E = (int64_t)T * 256;
+    double *out = partials + (int64_t)blockIdx.x * (EUC ? 2 * E : E);
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int t = wv + u * WAVES;
+        if (t < T) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                out[t * 256 + r * 64 + lane] = acc[u][r];
+                if (EUC) out[E + t * 256 + r * 64 + lane] = acce[EUC ? u : 0][r];
+            }
+        }
+    }
+    if (EUC) {
+        gmax[threadIdx.x] = bm;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double g = 0.0;
+            for (int i = 0; i < NTHR; ++i) g = gmax[i] > g ? gmax[i] : g;
+            bmax[blockIdx.x] = g;
+        }
+    }
+}
+
 // Batched form (Euclidean): workgroup b takes the rows of task b; pass > 1 reads the Q.
 template <int NP, int WAVES, bool F32>
 __global__ void __launch_bounds__(WAVES * 64)
@@ -1783,9 +1932,36 @@ static hipError_t launch_trsm_256(hipStream_t s, const Problem &p, const Work &w
     return hipGetLastError();
 }
 
+// Waves per workgroup of the CSR Gram: 4; at n = 256 the 136 tiles take 16 waves (9 tiles,
+// 72 accumulator registers each), or 8 for the first pass, whose second (Euclidean) set of
+// tiles would not fit 16 waves' registers.
+template <int NP>
+static hipError_t launch_gram_csr(hipStream_t s, const Problem &p, const Work &w, int pass, bool euc, int final_gram)
+{
+    constexpr int WE = NP == 256 ? 8 : 4, WB = NP == 256 ? 16 : 4;
+    dim3 grid(w.nwg);
+    if (euc)
+        hipLaunchKernelGGL((k_gram_csr<NP, WE, true>), grid, dim3(WE * 64), 0, s, p, w.partials, w.bmax, w.ctl, pass,
+                           final_gram);
+    else
+        hipLaunchKernelGGL((k_gram_csr<NP, WB, false>), grid, dim3(WB * 64), 0, s, p, w.partials, w.bmax, w.ctl,
+                           pass, final_gram);
+    return hipGetLastError();
+}
+
 static hipError_t gram_generic(hipStream_t s, const Problem &p, const Work &w, int pass, bool f32,
                                bool obl, bool euc, int final_gram)
 {
+    if (obl && p.brp) {
+        switch (p.np) {
+        case 16: return launch_gram_csr<16>(s, p, w, pass, euc, final_gram);
+        case 32: return launch_gram_csr<32>(s, p, w, pass, euc, final_gram);
+        case 64: return launch_gram_csr<64>(s, p, w, pass, euc, final_gram);
+        case 128: return launch_gram_csr<128>(s, p, w, pass, euc, final_gram);
+        case 256: return launch_gram_csr<256>(s, p, w, pass, euc, final_gram);
+        }
+        return hipErrorInvalidValue;
+    }
     switch (p.np) {
     case 16: return launch_gram_wide<16>(s, p, w, pass, f32, obl, euc, final_gram);
     case 32: return launch_gram_wide<32>(s, p, w, pass, f32, obl, euc, final_gram);
@@ -1842,7 +2018,9 @@ hipError_t launch_pass(hipStream_t s, const Problem &p, const Work &w, int mode,
             pg.X = p.Q;
             pg.ldx = p.ldq;
         }
-        prof_before(s, oblique_gram ? (euclid_too ? "gram_b_first" : "gram_b") : (fp32_gram ? "gram_f32" : "gram"));
+        prof_before(s, oblique_gram ? (p.brp ? (euclid_too ? "gram_csr_first" : "gram_csr")
+                                             : (euclid_too ? "gram_b_first" : "gram_b"))
+                                    : (fp32_gram ? "gram_f32" : "gram"));
         e = gram_generic(s, pg, w, pass, fp32_gram, oblique_gram, euclid_too, final_gram);
         prof_after(s);
     }

@@ -85,7 +85,8 @@ struct Ctl {
     int32_t redo_fp64;  // FP32-first: the first pass must be redone in binary64
     int32_t status;
     int32_t f32_pass;   // FP32-first: pass 1 factor came from the binary32 Gram
-    int32_t pad[2];
+    int32_t bad_b;      // a Gram kernel met an out-of-range index of a CSR B
+    int32_t pad;
     double bnorm;       // ||B||_2 bound (1 for B = I)
 };
 
@@ -101,6 +102,11 @@ struct Problem {
     int64_t ldr;
     const double *bdiag;   // tridiagonal B or nullptr
     const double *boff;
+    const int64_t *brp;    // CSR B (row pointers, columns, values) or nullptr
+    const int32_t *bcol;
+    const double *bval;
+    int64_t bnnz;
+    int32_t *bad_b;        // CSR index errors are flagged here (the control block)
     int32_t zero;          // always 0; opaque to the compiler (keeps loads inside loops)
     double gram_depth;     // bound on the summation depth of this problem's Grams
 };

@@ -117,6 +117,29 @@ def test_synchronous_argument_errors(L):
     o4.recompute = 2
     assert L.scqr_qr(None, 5000, 30, P, 30, None, 0x900000000, 30, 0x800000000, 30,
                      0x700000000, 1 << 30, ctypes.byref(o4), info) == scqr.E_INVALID
+    # CSR B: row pointers required; values and columns when nnz > 0; nnz >= 0
+    csr = scqr._SpdOp()
+    csr.kind = 2
+    csr.nnz = 10
+    args = (None, 5000, 30, P, 30, ctypes.byref(csr), 0x900000000, 30, 0x800000000, 30, 0x700000000, 1 << 30)
+    assert L.scqr_qr(*args, None, info) == scqr.E_INVALID  # no row_ptr
+    csr.row_ptr, csr.col = 0x600000000, 0x610000000
+    assert L.scqr_qr(*args, None, info) == scqr.E_INVALID  # no val
+    csr.val, csr.nnz = 0x620000000, -1
+    assert L.scqr_qr(*args, None, info) == scqr.E_INVALID  # negative nnz
+    csr.nnz = 10
+    o5 = scqr._Opts()
+    L.scqr_default_opts(ctypes.byref(o5))
+    o5.precision = 1
+    assert L.scqr_qr(*args, ctypes.byref(o5), info) == scqr.E_UNSUPPORTED
+    csr.kind = 3
+    assert L.scqr_qr(*args, None, info) == scqr.E_INVALID  # unknown kind
+    csr.kind = 2
+    sz5 = ctypes.c_size_t()
+    assert L.scqr_workspace_bytes(5000, 30, ctypes.byref(csr), None, ctypes.byref(sz5)) == scqr.OK
+    sz6 = ctypes.c_size_t()
+    assert L.scqr_workspace_bytes(5000, 30, None, None, ctypes.byref(sz6)) == scqr.OK
+    assert sz5.value > sz6.value  # the oblique first pass keeps a second (Euclidean) Gram
     # backward: dX aliasing Q
     assert L.scqr_qr_backward(None, 5000, 30, P, 30, 0x800000000, 30, None, 30, None, 30, P, 30,
                               0x700000000, 1 << 30) == scqr.E_INVALID
