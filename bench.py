@@ -6,12 +6,17 @@ Default workload: X = U diag(sigma) V^T with m = 2^22, n = 64, sigma geometric f
 Algorithm 2 continuation) with the paper's shift (eq:finds2).  One step = one complete
 factorization X -> (Q, R) with X resident in HBM.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2|c2b|c1|c3] [--no-extras]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2|c2b|c1|c3|c5|f1|f3|c4]
+                  [--no-extras]
 
 With the default workload the line also carries ``extras``, timed with HIP events on the
 launch stream (inputs generated on the host by the seeded generators, then resident in HBM):
   c2b  CholeskyQR2 vs shiftedCholeskyQR3 (Algorithm 3) at kappa = 1e6 (same accuracy bar);
   c3   oblique factorization, 1e6 x 128, kappa = 1e13, tridiagonal SPD B;
+  f1   oblique factorization with a sparse SPD B in compressed sparse rows (stencil and random
+       banded patterns standing in for the SuiteSparse matrices), 1e6 rows;
+  f2   the summation-depth shift against the paper's shift on the default workload;
+  f3   minimum-traffic passes (recomputing each pass's input from X) against stored passes;
   c4   512 uneven instances (m_i in [1e4, 2e5], n_i in {16, 32, 64, 128}, kappa_i in
        [1e4, 1e15]): one batched call vs a loop of single calls, and FP32-first vs FP64;
   c5   2^20 x 256, kappa = 1e8: forward (Algorithm 3) and the hand-written adjoint.
@@ -47,6 +52,8 @@ WORKLOADS = {
     "c5": (1 << 20, 256, 1e8, False, "randsvd m=1048576 n=256 kappa=1e8 fp64, adaptive schedule, paper shift"),
     "f3": (1 << 23, 32, 1e15, False, "randsvd m=8388608 n=32 kappa=1e15 fp64, adaptive schedule, paper shift, "
                                      "minimum-traffic passes"),
+    "f1": (1000000, 64, 1e13, True, "randsvd m=1000000 n=64 kappa=1e13, sparse SPD B in compressed sparse rows "
+                                    "(3-D 27-point pattern, about 26 entries per row), fp64, adaptive schedule"),
     "c4": (0, 0, 0.0, False, "512 instances m_i in [1e4, 2e5], n_i in {16, 32, 64, 128}, kappa_i in [1e4, 1e15], "
                              "one batched call, fp64"),
 }
@@ -277,6 +284,67 @@ def extra_f3(scqr, synth):
     return out
 
 
+def _csr_dev(scqr, B):
+    import torch
+
+    return scqr.CsrB(torch.from_numpy(B.row_ptr).cuda(), torch.from_numpy(B.col).cuda(),
+                     torch.from_numpy(B.val).cuda())
+
+
+def csr_b(synth, kind, m, seed):
+    """The sparse SPD B of a CSR workload: '5pt', '27pt' stencil patterns or 'rand' (48 entries per
+    row within 4096 rows of the diagonal)."""
+    if kind == "rand":
+        return synth.random_pattern_b(m, 48, 4096, seed=seed)
+    return synth.stencil_b(m, kind, seed=seed)
+
+
+def extra_f1(scqr, synth):
+    """Oblique factorization with a general sparse SPD B in compressed sparse rows (Section 7) on
+    stand-ins for the SuiteSparse matrices: 10^6 rows, 5-point (about 5 entries per row, like
+    apache2 or G3_circuit), 27-point (about 26, like shipsec8) and random banded (about 47, like
+    bone010 or serena) patterns, n = 64, plus n = 16 and 256 on the 27-point pattern; kappa = 1e13,
+    adaptive schedule.  Time per factorization, passes, and per kernel the B-Gram against its
+    minimum traffic (X, the CSR arrays) and the substitution."""
+    import torch
+
+    m = 1000000
+    out = {}
+    for kind, n in (("5pt", 64), ("27pt", 64), ("rand", 64), ("27pt", 16), ("27pt", 256)):
+        B = csr_b(synth, kind, m, seed=synth.seed_for(6, 1))
+        X = torch.from_numpy(synth.randsvd(m, n, 1e13, seed=synth.seed_for(6, n))).cuda()
+        Bd = _csr_dev(scqr, B)
+        plan = scqr.Plan(m, n, "cuda", B=Bd, schedule="adaptive")
+        ms = _time_ms(lambda: plan.run(X), reps=5)
+        info = plan.read_info()
+        scqr.profile_enable(True)
+        plan.run(X)
+        torch.cuda.synchronize()
+        recs = scqr.profile_read()
+        scqr.profile_enable(False)
+        by = {}
+        for name, dur in recs:
+            if dur > 0.005:  # launches that ran (gated passes return at once)
+                by.setdefault(name, []).append(dur)
+        p = info.passes
+        nnz = B.nnz
+        fl = p * (m * n * (n + 1) + m * n * n + 2 * nnz * n) + m * n * (n + 1)
+        gb = 8 * m * n + 12 * nnz + 8 * (m + 1)
+        r = {"ms": round(ms, 4), "passes": p, "status": scqr.status_string(info.status),
+             "nnz_per_row": round(nnz / m, 2), "TFLOP/s": round(fl / ms / 1e9, 3), "bnorm": info.bnorm}
+        for k in ("gram_csr_first", "gram_csr", "trsm"):
+            if k in by:
+                avg = float(sum(by[k]) / len(by[k]))
+                r[k] = {"launches": len(by[k]), "avg_ms": round(avg, 4)}
+                if k.startswith("gram_csr"):
+                    r[k]["GB/s_min_traffic"] = round(gb / avg / 1e6, 1)
+                    r[k]["gathered_GB/s"] = round(8 * nnz * n / avg / 1e6, 1)
+        out[f"{kind} n={n}"] = r
+        del plan, X, Bd, B
+        torch.cuda.empty_cache()
+    return out
+
+
 def extra_c3(scqr, synth):
     import torch
 
@@ -441,9 +509,12 @@ KERNEL_PATTERNS = [
     ("b_gram_np", r"k_gram_wide<(\d+), false, false, false, true>"),
     ("b_chol", r"k_chol_b<"),
     ("b_reduce", r"k_reduce_b\("),
-    ("trsm_gram", r"k_pass_tile<\d+, 1, false, (true|false), 32(, false)?>"),
-    ("trsm_gram_mt", r"k_pass_tile<\d+, 5, false, (true|false), 32(, false)?>"),
-    ("gram", r"k_pass_tile<\d+, 0, false, (true|false), 32(, false)?>"),
+    ("trsm_gram", r"k_pass_tile<\d+, 1, false, (true|false), (32|64)(, false)?>"),
+    ("trsm_gram_mt", r"k_pass_tile<\d+, 5, false, (true|false), (32|64)(, false)?>"),
+    ("gram", r"k_pass_tile<\d+, 0, (true|false), (true|false), (32|64)(, false)?>"),
+    ("trsm", r"k_pass_tile<\d+, 2, false, (true|false), (32|64)(, false)?>"),
+    ("gram_csr_first", r"k_gram_csr<\d+, \d+, true>"),
+    ("gram_csr", r"k_gram_csr<\d+, \d+, false>"),
     ("trsm_gram", r"k_pass_wide<\d+, 1, (true|false)>"),
     ("trsm", r"k_pass_wide<\d+, 2, (true|false)>"),
     ("trsm_half1", r"k_pass_wide4<"),
@@ -457,7 +528,7 @@ KERNEL_PATTERNS = [
 ]
 
 
-def alg_bytes(short, m, n, class_mn=None):
+def alg_bytes(short, m, n, class_mn=None, nnz=None):
     """Algorithmic HBM bytes of one launch: a fused pass or a substitution reads its input and
     writes Q (16 m n; 8 m n for the second half of the n = 256 block solve), a Gram reads its
     input (8 m n; + 16 m for B's two diagonals), the first half of the n = 256 block solve reads
@@ -467,6 +538,10 @@ def alg_bytes(short, m, n, class_mn=None):
         np_ = int(short.rsplit("_np", 1)[1])
         per = 16 if short.startswith("b_trsm_gram") else 8
         return per * class_mn.get(np_, 0)
+    if short.startswith("gram_csr"):
+        # X once, the CSR arrays once (8-byte value, 4-byte column, 8-byte row pointer); the
+        # gathered rows of X are re-reads that the caches are expected to serve
+        return None if nnz is None else 8 * m * n + 12 * nnz + 8 * (m + 1)
     return {"trsm_gram": 16 * m * n, "trsm": 16 * m * n if n <= 128 else 8 * m * n, "trsm_half1": 16 * m * n,
             "gram": 8 * m * n, "gram_b": 8 * m * n + 16 * m, "gram_b_first": 8 * m * n + 16 * m}.get(short)
 
@@ -698,7 +773,7 @@ def main():
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="write profiles/<kernel>_<workload>.md and _counters.json from the rocprofv3 "
                          "outputs under DIR (trace/, fetch/, write/, cfetch/, cwrite/)")
-    ap.add_argument("--extras", default="c2b,f2,f3,c3,c4,c5")
+    ap.add_argument("--extras", default="c2b,f1,f2,f3,c3,c4,c5")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -733,11 +808,16 @@ def main():
     t = time.perf_counter()
     if args.workload == "f3":
         X = synth.randsvd(m, n, kappa, seed=synth.seed_for(9, n))
+    elif args.workload == "f1":
+        X = synth.randsvd(m, n, kappa, seed=synth.seed_for(6, n))
     else:
         cfg_index = {"c1": 0, "c2": 1, "c2b": 1, "c3": 2, "c5": 4}[args.workload]
         X = synth.randsvd(m, n, kappa, seed=synth.seed_for(cfg_index))
-    B = None
-    if oblique:
+    B, Bh = None, None
+    if args.workload == "f1":
+        Bh = csr_b(synth, "27pt", m, seed=synth.seed_for(6, 1))
+        B = _csr_dev(scqr, Bh)
+    elif oblique:
         d, o = synth.tridiag_b(m, seed=synth.seed_for(cfg_index, 1))
         B = (torch.from_numpy(d).cuda(), torch.from_numpy(o).cuda())
     Xd = torch.from_numpy(X).cuda()
@@ -789,8 +869,12 @@ def main():
     dom = max(kstats, key=lambda k: kstats[k]["total_ms"])
     avg = kstats[dom]["avg_active_ms"]
     # algorithmic bytes per launch of the dominant kernel
+    csr_bytes = 8 * m * n + 12 * Bh.nnz + 8 * (m + 1) if Bh is not None else 0
     unit_bytes = {"trsm_gram": 16 * m * n, "trsm": 16 * m * n, "gram": 8 * m * n,
-                  "gram_b": 8 * m * n + 16 * m, "gram_b_first": 8 * m * n + 16 * m}.get(dom, 16 * m * n)
+                  "gram_b": 8 * m * n + 16 * m, "gram_b_first": 8 * m * n + 16 * m,
+                  "gram_csr": csr_bytes, "gram_csr_first": csr_bytes,
+                  # every pass reads X, the last one also writes Q
+                  "trsm_gram_mt": 8 * m * n * (p + 1) // max(p, 1)}.get(dom, 16 * m * n)
     achieved = unit_bytes / (avg * 1e-3) / 1e9
     traffic = traffic_from_profiles(dom, args.workload, unit_bytes)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -831,10 +915,10 @@ def main():
 
         t = time.perf_counter()
         Qh, Rh = plan.Q.cpu().numpy(), plan.R.cpu().numpy()
-        tri = None
-        if oblique:
-            tri = (d, o)
-        om2, omf = accuracy.orthogonality(Qh, tri)
+        if Bh is not None:
+            om2, omf = accuracy.orthogonality(Qh, csr=(Bh.row_ptr, Bh.col, Bh.val))
+        else:
+            om2, omf = accuracy.orthogonality(Qh, (d, o) if oblique else None)
         res = accuracy.residual(X, Qh, Rh)
         result["accuracy"] = {"orthogonality_2": om2, "orthogonality_F": omf, "residual": res}
         log(f"[bench] accuracy: ||Q^TQ-I||_2={om2:.2e} residual={res:.2e} ({time.perf_counter() - t:.1f} s)")
@@ -847,8 +931,8 @@ def main():
         result["cpu_baseline"]["value"] = round(cb["value"], 5)
         log(f"[bench] cpu baseline: {cb['value'] * 1e3:.2f} GFLOP/s on {cb['cores']} threads")
     if args.workload == "c2" and not args.no_extras:
-        fns = {"c2b": extra_c2b, "f2": extra_f2, "f3": extra_f3, "c3": extra_c3, "c4": extra_c4,
-               "c5": extra_c5}
+        fns = {"c2b": extra_c2b, "f1": extra_f1, "f2": extra_f2, "f3": extra_f3, "c3": extra_c3,
+               "c4": extra_c4, "c5": extra_c5}
         extras, speed = {}, {}
         for name in [x for x in args.extras.split(",") if x]:
             t = time.perf_counter()

@@ -96,11 +96,21 @@ struct Layout {
         off_split, total;
 };
 
-Layout layout(int64_t m, int64_t n, bool oblique)
+// csr: the sparse-B Gram gathers rows of X with long latencies, so it runs more workgroups
+// (four per workgroup of the pass kernels up to n = 64, two at n = 128; each one sums its own
+// partial Gram) to keep more of them in flight.
+Layout layout(int64_t m, int64_t n, bool oblique, bool csr = false)
 {
     Layout L;
     L.np = padded_n(n);
     L.nwg = pass_grid(m, L.np);
+    if (csr) {
+        const int f = L.np <= 64 ? 4 : (L.np == 128 ? 2 : 1);
+        const int64_t panels = (m + 15) / 16;
+        int64_t g = (int64_t)L.nwg * f;
+        if (g > panels) g = panels;
+        if (g > L.nwg) L.nwg = (int)g;
+    }
     L.nlvl2 = (L.nwg + 31) / 32;
     L.elems = pass_partial_elems(L.np, oblique);
     const size_t np = (size_t)L.np;
@@ -156,6 +166,7 @@ Work carve(void *ws, const Layout &L)
 }
 
 bool is_oblique(const scqr_spd_op *B) { return B && (B->kind == SCQR_B_TRIDIAG || B->kind == SCQR_B_CSR); }
+bool is_csr(const scqr_spd_op *B) { return B && B->kind == SCQR_B_CSR; }
 
 scqr_status check_B(const scqr_spd_op *B, int64_t m)
 {
@@ -574,7 +585,7 @@ scqr_status scqr_workspace_bytes(int64_t m, int64_t n, const scqr_spd_op *B, con
         scqr_status st = check_opts(opts);
         if (st != SCQR_OK) return st;
     }
-    *bytes = layout(m, n, is_oblique(B)).total;
+    *bytes = layout(m, n, is_oblique(B), is_csr(B)).total;
     return SCQR_OK;
 }
 
@@ -611,7 +622,7 @@ scqr_status qr_enqueue(void *stream, int64_t m, int64_t n, const double *X, int6
     if (Q != X && ranges_overlap(X, xb, Q, qb)) return SCQR_E_INVALID;
     if (Q == X && ldq != ldx) return SCQR_E_INVALID;
     if (ranges_overlap(R, rb, X, xb) || ranges_overlap(R, rb, Q, qb)) return SCQR_E_INVALID;
-    const Layout L = layout(m, n, obl);
+    const Layout L = layout(m, n, obl, is_csr(B));
     if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return SCQR_E_WORKSPACE;
     if (ranges_overlap(ws, L.total, R, rb) || ranges_overlap(ws, L.total, Q, qb) ||
         ranges_overlap(ws, L.total, X, xb))
@@ -724,7 +735,7 @@ scqr_status scqr_qr_noalloc(void *stream, int64_t m, int64_t n, const double *X,
     scqr_status st = check_B(B, m);
     if (st != SCQR_OK) return st;
     if (opts && (st = check_opts(opts)) != SCQR_OK) return st;
-    if (layout(m, n, is_oblique(B)).total > kScratchBytes) return SCQR_E_WORKSPACE;
+    if (layout(m, n, is_oblique(B), is_csr(B)).total > kScratchBytes) return SCQR_E_WORKSPACE;
     void *ws = nullptr;
     st = scratch_for_current_device(&ws);
     if (st != SCQR_OK) return st;
@@ -740,7 +751,7 @@ scqr_status scqr_gram(void *stream, int64_t m, int64_t n, const double *X, int64
     scqr_status st = check_B(B, m);
     if (st != SCQR_OK) return st;
     const bool obl = is_oblique(B);
-    const Layout L = layout(m < n ? n : m, n, obl);
+    const Layout L = layout(m < n ? n : m, n, obl, is_csr(B));
     if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return SCQR_E_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Work w = carve(ws, L);

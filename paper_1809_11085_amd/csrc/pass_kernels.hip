@@ -1477,31 +1477,59 @@ k_gram_lds(Problem p, double *__restrict__ partials, double *__restrict__ bmax,
 // ------------------------------------------------------------------------------------------
 // Oblique Gram X^T B X for a general sparse B in compressed sparse rows (Section 7).  A
 // workgroup takes a contiguous share of 16-row panels.  For each panel it stages the rows of X
-// in LDS and forms the matching rows of Y = B X beside them: thread (r, c) sums, in storage
-// order, val_e x_{col_e, c} over the entries e of row r, the rows x_{col_e} gathered from HBM
-// (through L2) and read coalesced by the NP threads of the row, eight entries' loads issued
-// before their products are added.  The upper tiles of X^T Y then accumulate on FP64 MFMA as in
-// the tridiagonal kernels.  Y never reaches HBM: the blocked strategy of Section 7 with blocks
-// of 16 rows of Y (all n columns) instead of column blocks.
-//   EUC (first pass): also X^T X for ||X||_2 of (eq:finds2B) and the Gershgorin bound (largest
-//   absolute row sum, each row summed in storage order) of the workgroup's rows into bmax.
-// Row pointers outside [0, nnz] or decreasing, and columns outside [0, m), are never used as
-// addresses: the entry is skipped and *p.bad_b set.
-template <int NP, int WAVES, bool EUC>
-__global__ void __launch_bounds__(WAVES * 64)
+// in LDS, stages the panel's CSR entries (row pointers, then columns and values in chunks of
+// up to CSR_CHUNK entries) in LDS, and forms the matching rows of Y = B X beside X: the 16 rows
+// at once, TR = NTHR / 16 threads per row, thread tc of a row taking columns tc + TR q.  Each
+// output sums, in storage order, val_e x_{col_e, c} over the entries e of its row, the rows
+// x_{col_e} gathered from HBM through the caches (read coalesced by the TR threads of the row;
+// with the indices already in LDS, the loads of several entries are in flight together).  The
+// upper tiles of X^T Y then accumulate on FP64 MFMA as in the tridiagonal kernels.  Y never
+// reaches HBM: the blocked strategy of Section 7 with blocks of 16 rows of Y (all n columns)
+// instead of column blocks.
+//   KIND 0: X^T B X into partial slots of E = T * 256 doubles.
+//   KIND 1 (first pass): also X^T X for ||X||_2 of (eq:finds2B), slots of 2 E (X^T B X, then
+//   X^T X), and the Gershgorin bound (largest absolute row sum, each row summed in storage
+//   order) of the workgroup's rows into bmax.
+//   KIND 2 and 3 split KIND 1 over two launches where one set of tiles is all the registers
+//   hold (n = 256): 2 writes X^T B X into the first half of the 2 E slots, 3 the second half
+//   (X^T X, no gathers) and the Gershgorin bound.
+// Row pointers outside [0, nnz] or out of order, and columns outside [0, m), are never used as
+// addresses: the entries concerned are skipped and *p.bad_b set.
+constexpr int CSR_CHUNK = 1024;
+// Waves per SIMD the CSR Gram is compiled for (its loads wait on gathers; more waves in flight
+// hide more of that latency): 5 up to n = 64, 3 at n = 128; one fewer (no spills) with both sets
+// of tiles of the first pass.
+constexpr int csr_min_waves(int np, int kind)
+{
+    return (np <= 64 ? 5 : (np == 128 ? 3 : 1)) - (kind == 1 && np >= 64 ? 1 : 0);
+}
+
+template <int NP, int WAVES, int KIND>
+__global__ void __launch_bounds__(WAVES * 64, csr_min_waves(NP, KIND))
 k_gram_csr(Problem p, double *__restrict__ partials, double *__restrict__ bmax, const Ctl *__restrict__ ctl,
            int pass, int final_gram)
 {
     constexpr int NT = NP / 16;
     constexpr int T = NT * (NT + 1) / 2;
-    constexpr int TPW = (T + WAVES - 1) / WAVES;
+    constexpr bool BG = KIND != 3;                // X^T B X tiles (and the gathers for Y)
+    constexpr bool EUC = KIND == 1 || KIND == 3;  // X^T X tiles and the Gershgorin bound
+    // virtual tiles: with both sets, v < T is a tile of X^T B X and v >= T one of X^T X; wave w
+    // takes v = w + WAVES u.  Tile v goes to slot offset VOFF + v * 256.
+    constexpr int VT = (BG ? T : 0) + (EUC ? T : 0);
+    constexpr int64_t SLOT = (int64_t)(KIND == 0 ? 1 : 2) * T * 256;
+    constexpr int64_t VOFF = KIND == 3 ? (int64_t)T * 256 : 0;
+    constexpr int TPW = (VT + WAVES - 1) / WAVES;
     constexpr int PR = 16;
     constexpr int S = NP + 1;
     constexpr int NTHR = WAVES * 64;
-    constexpr int RPS = NTHR / NP;  // rows of Y formed per step
-    constexpr int GB = NP >= 256 ? 4 : 8;  // entries whose loads are issued together
-    static_assert(NTHR % NP == 0 && RPS >= 1 && PR % RPS == 0, "Y rows split evenly over the threads");
+    constexpr int TR = NTHR / PR;      // threads per row of Y
+    constexpr int CPT = NP / TR;       // columns per thread
+    constexpr int GB = NP == 256 ? 1 : (CPT >= 8 ? 2 : 4);  // entries whose loads are issued together
+    static_assert(NTHR % PR == 0 && CPT >= 1 && NP % TR == 0, "Y splits evenly over the threads");
     __shared__ double xs[PR * S], ys[PR * S];
+    __shared__ double sval[CSR_CHUNK];
+    __shared__ int32_t scol[CSR_CHUNK];
+    __shared__ int64_t rps[PR + 1];
     __shared__ double gmax[NTHR];
 
     if (!gate(ctl, pass)) return;
@@ -1511,23 +1539,20 @@ k_gram_csr(Problem p, double *__restrict__ partials, double *__restrict__ bmax, 
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n = p.n;
     const int64_t m = p.m;
-    const int c = threadIdx.x % NP, rs = threadIdx.x / NP;
+    const int r = threadIdx.x / TR, tc = threadIdx.x % TR;
     const int64_t npanels = (m + PR - 1) / PR;
     const int64_t per = (npanels + gridDim.x - 1) / gridDim.x;
     const int64_t p0 = (int64_t)blockIdx.x * per;
     const int64_t p1 = (p0 + per < npanels) ? p0 + per : npanels;
 
-    d4 acc[TPW], acce[EUC ? TPW : 1];
+    d4 acc[TPW];
 #pragma unroll
     for (int u = 0; u < TPW; ++u) acc[u] = (d4){0.0, 0.0, 0.0, 0.0};
-    if (EUC) {
-#pragma unroll
-        for (int u = 0; u < (EUC ? TPW : 1); ++u) acce[u] = (d4){0.0, 0.0, 0.0, 0.0};
-    }
     int ti[TPW], tj[TPW];
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
-        const int t = wv + u * WAVES < T ? wv + u * WAVES : 0;
+        const int v = wv + u * WAVES < VT ? wv + u * WAVES : 0;
+        const int t = v < T ? v : v - T;
         ti[u] = 16 * tile_row(NT, t);
         tj[u] = 16 * tile_col(NT, t);
     }
@@ -1536,52 +1561,78 @@ k_gram_csr(Problem p, double *__restrict__ partials, double *__restrict__ bmax, 
 
     for (int64_t pn = p0; pn < p1; ++pn) {
         const int64_t r0 = pn * PR;
+        const int nr = (int)((m - r0 < PR) ? m - r0 : PR);
         __syncthreads();
         for (int idx = threadIdx.x; idx < PR * NP; idx += NTHR) {
             const int rr = idx / NP, cc = idx % NP;
             const int64_t row = r0 + rr;
             xs[rr * S + cc] = (row < m && cc < n) ? as_global(p.X)[row * p.ldx + cc] : 0.0;
         }
-        for (int rr = rs; rr < PR; rr += RPS) {
-            const int64_t row = r0 + rr;
-            double y = 0.0, asum = 0.0;
-            if (row < m) {
-                int64_t e0 = as_global(p.brp)[row], e1 = as_global(p.brp)[row + 1];
-                if (!(e0 >= 0 && e0 <= e1 && e1 <= p.bnnz)) {
-                    bad = true;
-                    e1 = e0;
-                }
-                for (int64_t e = e0; e < e1; e += GB) {
-                    int32_t js[GB];
-                    double vs[GB], xv[GB];
+        if (threadIdx.x <= nr) rps[threadIdx.x] = as_global(p.brp)[r0 + threadIdx.x];
+        __syncthreads();
+        // entries of the panel: [lo, hi); row r's: [e0, e1) inside it
+        const int64_t lo = rps[0], hi = rps[nr];
+        const bool panel_ok = lo >= 0 && lo <= hi && hi <= p.bnnz;
+        int64_t e0 = 0, e1 = 0;
+        if (r < nr && panel_ok) {
+            e0 = rps[r];
+            e1 = rps[r + 1];
+            if (!(e0 >= lo && e0 <= e1 && e1 <= hi)) {
+                bad = true;
+                e1 = e0;
+            }
+        }
+        if (!panel_ok) bad = true;
+        double y[CPT];
 #pragma unroll
-                    for (int u = 0; u < GB; ++u) {
-                        js[u] = -1;
-                        vs[u] = 0.0;
-                        if (e + u < e1) {
-                            const int32_t j = as_global(p.bcol)[e + u];
-                            vs[u] = as_global(p.bval)[e + u];
-                            if (j >= 0 && (int64_t)j < m)
-                                js[u] = j;
-                            else
-                                bad = true;
+        for (int q = 0; q < CPT; ++q) y[q] = 0.0;
+        double asum = 0.0;
+        const int64_t hi_ok = panel_ok ? hi : lo;
+        for (int64_t cs = lo; cs < hi_ok; cs += CSR_CHUNK) {
+            const int cnt = (int)((hi_ok - cs < CSR_CHUNK) ? hi_ok - cs : CSR_CHUNK);
+            __syncthreads();
+            for (int i = threadIdx.x; i < cnt; i += NTHR) {
+                const int32_t j = as_global(p.bcol)[cs + i];
+                const bool jok = j >= 0 && (int64_t)j < m;
+                if (!jok) bad = true;
+                scol[i] = jok ? j : -1;
+                sval[i] = as_global(p.bval)[cs + i];
+            }
+            __syncthreads();
+            const int a = (int)((e0 > cs ? e0 : cs) - cs);
+            const int b = (int)((e1 < cs + cnt ? e1 : cs + cnt) - cs);
+            for (int e = a; e < b; e += GB) {
+                double xv[GB][CPT], vv[GB];
+                bool ok[GB];
+#pragma unroll
+                for (int u = 0; u < GB; ++u) {
+                    const int j = (e + u < b) ? scol[e + u] : -1;
+                    ok[u] = j >= 0;
+                    vv[u] = ok[u] ? sval[e + u] : 0.0;
+                    if constexpr (BG) {
+                        const auto xr = as_global(p.X) + (int64_t)(ok[u] ? j : 0) * p.ldx;
+#pragma unroll
+                        for (int q = 0; q < CPT; ++q) {
+                            const int cc = tc + TR * q;
+                            xv[u][q] = (ok[u] && cc < n) ? xr[cc] : 0.0;
                         }
                     }
+                }
 #pragma unroll
-                    for (int u = 0; u < GB; ++u)
-                        xv[u] = (js[u] >= 0 && c < n) ? as_global(p.X)[(int64_t)js[u] * p.ldx + c] : 0.0;
+                for (int u = 0; u < GB; ++u) {
+                    if (ok[u]) {
+                        if constexpr (BG) {
 #pragma unroll
-                    for (int u = 0; u < GB; ++u) {
-                        if (js[u] >= 0) {
-                            y = __builtin_fma(vs[u], xv[u], y);
-                            if (EUC) asum += fabs(vs[u]);
+                            for (int q = 0; q < CPT; ++q) y[q] = __builtin_fma(vv[u], xv[u][q], y[q]);
                         }
+                        if (EUC) asum += fabs(vv[u]);
                     }
                 }
             }
-            ys[rr * S + c] = y;
-            if (EUC && c == 0) bm = asum > bm ? asum : bm;
         }
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) ys[r * S + tc + TR * q] = y[q];
+        if (EUC && tc == 0 && r < nr) bm = asum > bm ? asum : bm;
         __syncthreads();
 #pragma unroll
         for (int s4 = 0; s4 < PR / 4; ++s4) {
@@ -1590,26 +1641,23 @@ k_gram_csr(Problem p, double *__restrict__ partials, double *__restrict__ bmax, 
             const double *yrow = ys + rr * S + (lane & 15);
 #pragma unroll
             for (int u = 0; u < TPW; ++u) {
-                if (wv + u * WAVES < T) {
-                    const double a = xrow[ti[u]];
-                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, yrow[tj[u]], acc[u], 0, 0, 0);
-                    if (EUC) acce[EUC ? u : 0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xrow[tj[u]], acce[EUC ? u : 0], 0, 0, 0);
+                const int v = wv + u * WAVES;
+                if (v < VT) {
+                    const double bv = (BG && v < T) ? yrow[tj[u]] : xrow[tj[u]];
+                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xrow[ti[u]], bv, acc[u], 0, 0, 0);
                 }
             }
         }
     }
     if (bad) *p.bad_b = 1;
-    constexpr int64_t E = (int64_t)T * 256;
-    double *out = partials + (int64_t)blockIdx.x * (EUC ? 2 * E : E);
+    double *out = partials + (int64_t)blockIdx.x * SLOT + VOFF;
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
-        const int t = wv + u * WAVES;
-        if (t < T) {
+        const int v = wv + u * WAVES;
+        if (v < VT) {
+            // KIND 1: X^T B X at [0, E), X^T X at [E, 2 E)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                out[t * 256 + r * 64 + lane] = acc[u][r];
-                if (EUC) out[E + t * 256 + r * 64 + lane] = acce[EUC ? u : 0][r];
-            }
+            for (int rr = 0; rr < 4; ++rr) out[(int64_t)v * 256 + rr * 64 + lane] = acc[u][rr];
         }
     }
     if (EUC) {
@@ -1932,20 +1980,27 @@ static hipError_t launch_trsm_256(hipStream_t s, const Problem &p, const Work &w
     return hipGetLastError();
 }
 
-// Waves per workgroup of the CSR Gram: 4; at n = 256 the 136 tiles take 16 waves (9 tiles,
-// 72 accumulator registers each), or 8 for the first pass, whose second (Euclidean) set of
-// tiles would not fit 16 waves' registers.
+// Waves per workgroup of the CSR Gram: 4 at n <= 16 (one column per thread), 8 up to n = 128;
+// at n = 256 the 136 tiles take 16 waves (9 tiles, 72 accumulator registers each), and the
+// first pass's two sets of tiles take two launches (KIND 2, then 3).
 template <int NP>
 static hipError_t launch_gram_csr(hipStream_t s, const Problem &p, const Work &w, int pass, bool euc, int final_gram)
 {
-    constexpr int WE = NP == 256 ? 8 : 4, WB = NP == 256 ? 16 : 4;
-    dim3 grid(w.nwg);
-    if (euc)
-        hipLaunchKernelGGL((k_gram_csr<NP, WE, true>), grid, dim3(WE * 64), 0, s, p, w.partials, w.bmax, w.ctl, pass,
-                           final_gram);
-    else
-        hipLaunchKernelGGL((k_gram_csr<NP, WB, false>), grid, dim3(WB * 64), 0, s, p, w.partials, w.bmax, w.ctl,
-                           pass, final_gram);
+    constexpr int W = NP <= 16 ? 4 : (NP == 256 ? 16 : 8);
+    dim3 grid(w.nwg), block(W * 64);
+    if (euc) {
+        if constexpr (NP == 256) {
+            hipLaunchKernelGGL((k_gram_csr<NP, W, 2>), grid, block, 0, s, p, w.partials, w.bmax, w.ctl, pass,
+                               final_gram);
+            hipLaunchKernelGGL((k_gram_csr<NP, W, 3>), grid, block, 0, s, p, w.partials, w.bmax, w.ctl, pass,
+                               final_gram);
+        } else {
+            hipLaunchKernelGGL((k_gram_csr<NP, W, 1>), grid, block, 0, s, p, w.partials, w.bmax, w.ctl, pass,
+                               final_gram);
+        }
+    } else {
+        hipLaunchKernelGGL((k_gram_csr<NP, W, 0>), grid, block, 0, s, p, w.partials, w.bmax, w.ctl, pass, final_gram);
+    }
     return hipGetLastError();
 }
 
