@@ -615,6 +615,49 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
         // ---- substitution of rows 16 wv .. 16 wv + 15, block by block: the block's MFMA update
         // from the solved blocks, then the diagonal solve in the result layout
         const int R0 = 16 * wv;
+        if constexpr (MODE == 1 || MODE == 2) {
+            // (MODE 4 keeps the block-by-block order: its -R~_12 slice leaves no registers for
+            // the eight blocks.)  Right-looking: every block T_J of the wave's rows stays in registers (the MFMA
+            // result layout); once block K is solved, its product with -R~_KJ is added to each
+            // later T_J.  Each T_J still receives X_J - Q_0 R~_0J - Q_1 R~_1J - ... in the order
+            // K = 0, 1, ... (and k-steps s4 = 0..3), as in the block-by-block order, but the
+            // updates of different J are independent MFMA chains.
+            d4 tb[NT];
+#pragma unroll
+            for (int J = 0; J < NT; ++J)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) tb[J][r] = P[(R0 + lk + 4 * r) * S + 16 * J + li];
+            const double *arow = P + (R0 + li) * S + lk;
+            // solve block K and store Q_K for the A operands of the updates
+            auto solve_store = [&](d4 &t, int K) {
+                double cf[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) cf[k] = dtab[(K * 16 + k) * 16 + li];
+                const double dj = dtab[NT * 256 + 16 * K + li];
+                diag_solve_steps<0, true>(t, cf);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) P[(R0 + lk + 4 * r) * S + 16 * K + li] = t[r] * dj;
+            };
+            auto update = [&](d4 &t, int K, int J) {
+                const int pi = J * (J - 1) / 2 + K;
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4)
+                    t = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * K + 4 * s4], bl[(pi * 4 + s4) * 64 + lane], t, 0,
+                                                             0, 0);
+            };
+            solve_store(tb[0], 0);
+            wave_sync();
+#pragma unroll
+            for (int K = 0; K + 1 < NT; ++K) {
+                // T_{K+1} is complete after Q_K's update; the updates of the later blocks by Q_K
+                // do not depend on its solve
+                update(tb[K + 1], K, K + 1);
+#pragma unroll
+                for (int J = K + 2; J < NT; ++J) update(tb[J], K, J);
+                solve_store(tb[K + 1], K + 1);
+                wave_sync();
+            }
+        } else
 #pragma unroll
         for (int it = 0; it < NT; ++it) {
             const int J = MODE == 3 ? NT - 1 - it : it;
