@@ -582,6 +582,11 @@ def summarize_profile(d, workload):
             while np_ < sp.n:
                 np_ *= 2
             class_mn[np_] = class_mn.get(np_, 0) + sp.m * sp.n
+    nnz = None
+    if workload == "f1":
+        import synth
+
+        nnz = csr_b(synth, "27pt", m, seed=synth.seed_for(6, 1)).nnz
     trace = rows("trace", "run_kernel_trace.csv")
     stats = rows("trace", "run_kernel_stats.csv")
     per = {}
@@ -629,7 +634,7 @@ def summarize_profile(d, workload):
             f, w_ = fetch[sn]["FETCH_SIZE"], write[sn]["WRITE_SIZE"]
             k.update({"fetch_kib_per_launch": f, "write_kib_per_launch": w_,
                       "hbm_bytes_per_launch": f * 1024 * fs + w_ * 1024 * ws})
-        alg = alg_bytes(sn, m, n, class_mn)
+        alg = alg_bytes(sn, m, n, class_mn, nnz)
         if alg:
             k["algorithmic_bytes_per_launch"] = alg
             k["achieved_GBs"] = alg / (k["avg_active_ms_rocprof"] * 1e-3) / 1e9
