@@ -513,8 +513,8 @@ KERNEL_PATTERNS = [
     ("trsm_gram_mt", r"k_pass_tile<\d+, 5, false, (true|false), (32|64)(, false)?>"),
     ("gram", r"k_pass_tile<\d+, 0, (true|false), (true|false), (32|64)(, false)?>"),
     ("trsm", r"k_pass_tile<\d+, 2, false, (true|false), (32|64)(, false)?>"),
-    ("gram_csr_first", r"k_gram_csr<\d+, \d+, true>"),
-    ("gram_csr", r"k_gram_csr<\d+, \d+, false>"),
+    ("gram_csr_first", r"k_gram_csr<\d+, \d+, [123]>"),
+    ("gram_csr", r"k_gram_csr<\d+, \d+, 0>"),
     ("trsm_gram", r"k_pass_wide<\d+, 1, (true|false)>"),
     ("trsm", r"k_pass_wide<\d+, 2, (true|false)>"),
     ("trsm_half1", r"k_pass_wide4<"),
