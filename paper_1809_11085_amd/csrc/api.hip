@@ -93,7 +93,7 @@ struct Layout {
     int np, nwg, nlvl2;
     int64_t elems;
     size_t off_ctl, off_G, off_Ge, off_Rt, off_dinv, off_R0, off_R1, off_part, off_lvl2, off_gsum, off_bmax,
-        off_split, total;
+        off_vprev, off_split, total;
 };
 
 // csr: the sparse-B Gram gathers rows of X with long latencies, so it runs more workgroups
@@ -137,6 +137,8 @@ Layout layout(int64_t m, int64_t n, bool oblique, bool csr = false)
     o += align256(sizeof(double) * (size_t)L.elems);
     L.off_bmax = o;
     o += align256(sizeof(double) * (size_t)L.nwg);
+    L.off_vprev = o;
+    o += align256(sizeof(double) * np);
     L.off_split = o;
     if (L.np == 256) o += align256(sizeof(double) * (2 * 128 * 128 + 2 * 128));
     L.total = o;
@@ -158,6 +160,7 @@ Work carve(void *ws, const Layout &L)
     w.lvl2 = reinterpret_cast<double *>(c + L.off_lvl2);
     w.gsum = reinterpret_cast<double *>(c + L.off_gsum);
     w.bmax = reinterpret_cast<double *>(c + L.off_bmax);
+    w.vprev = reinterpret_cast<double *>(c + L.off_vprev);
     w.Rsplit = L.np == 256 ? reinterpret_cast<double *>(c + L.off_split) : nullptr;
     w.nwg = L.nwg;
     w.nlvl2 = L.nlvl2;
@@ -238,6 +241,7 @@ size_t inst_block_bytes(int np, int slots)
     b += align256(sizeof(double) * np * np * slots);
     b += align256(sizeof(double) * np * slots);
     b += align256(sizeof(double) * (size_t)pass_partial_elems(np, false));
+    b += align256(sizeof(double) * np);
     if (np > 128) b += align256(sizeof(double) * np * (np + 1)) + 2 * align256(sizeof(double) * np * np);
     return b;
 }
@@ -411,6 +415,8 @@ void build_descriptors(const BatchArgs &a, const BatchPlan &bp, std::vector<unsi
             o2 += align256(sizeof(double) * np * bp.slots);
             I.w.gsum = reinterpret_cast<double *>(blk + o2);
             o2 += align256(sizeof(double) * elems);
+            I.w.vprev = reinterpret_cast<double *>(blk + o2);
+            o2 += align256(sizeof(double) * np);
             if (np > 128) {
                 I.w.G = reinterpret_cast<double *>(blk + o2);
                 o2 += align256(sizeof(double) * np * (np + 1));

@@ -144,7 +144,7 @@ __device__ __forceinline__ void block_sum3(double &a, double &b, double &c, doub
 // Power iteration of the first wave for NP <= 64 with row i of G held in lane i's registers
 // and the iterate broadcast from LDS (the stopping rule and start vector of power_lambda).
 template <int NP>
-__device__ double power_lambda_regs(const double *G, int S, int n, double *v)
+__device__ double power_lambda_regs(const double *G, int S, int n, double *v, const double *v0)
 {
     const int lane = threadIdx.x & 63;
     const int row = lane < NP ? lane : NP - 1;
@@ -152,7 +152,7 @@ __device__ double power_lambda_regs(const double *G, int S, int n, double *v)
     double g[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) g[k] = (act && k < n) ? G[row * S + k] : 0.0;
-    double vi = act ? 1.0 / sqrt((double)n) : 0.0;
+    double vi = act ? (v0 ? v0[lane] : 1.0 / sqrt((double)n)) : 0.0;
     if (lane < NP) v[lane] = vi;
     wave_sync_c();
     double lam = 0.0;
@@ -260,7 +260,7 @@ __device__ __forceinline__ int chol_wave_regs(double *G, int S, int n, double s,
 // the two sums per iteration are reduced in a fixed order (DPP within each wave, then the four
 // wave sums in order), so every thread holds the same values.
 template <int NP>
-__device__ double power_lambda_block(const double *G, int S, int n, double *v, double *red)
+__device__ double power_lambda_block(const double *G, int S, int n, double *v, double *red, const double *v0s)
 {
     static_assert(NP == 128 || NP == 256, "block power iteration");
     constexpr int H = NP == 128 ? 2 : 1;       // threads per row
@@ -273,7 +273,8 @@ __device__ double power_lambda_block(const double *G, int S, int n, double *v, d
 #pragma unroll
         for (int k = 0; k < CW; ++k) g[k] = (act && CW * h + k < n) ? G[row * S + CW * h + k] : 0.0;
     }
-    const double v0 = act ? 1.0 / sqrt((double)n) : 0.0;
+    const double v0 = act ? (v0s ? v0s[row] : 1.0 / sqrt((double)n)) : 0.0;
+    __syncthreads();  // v0s may share storage with v
     if (h == 0) v[row] = v0;
     __syncthreads();
     double vi = v0, lam = 0.0;
@@ -333,19 +334,21 @@ __device__ double power_lambda_block(const double *G, int S, int n, double *v, d
 }
 
 // ||X||_2^2 estimate (normest's rule: Rayleigh-quotient power iteration on the Gram from the
-// start vector 1/sqrt(n), stopped at a relative change <= 1e-6 or after 100 iterations; a lower
-// bound of lambda_max).  NP <= 64: the first wave alone, the result broadcast through LDS.
+// start vector 1/sqrt(n), or the unit vector v0 when given, stopped at a relative change <= 1e-6
+// or after 100 iterations; a lower bound of lambda_max for any start vector).  NP <= 64: the
+// first wave alone, the result broadcast through LDS.  The last iterate is left in v.
 // Returns -1 when an iterate falls in the null space of the computed Gram (G v = 0 in
 // floating point); the caller then takes the trace instead (||X||_F^2, Section 4.1).
 template <int NP>
-__device__ __forceinline__ double power_lambda(const double *G, int S, int n, double *v, double *red)
+__device__ __forceinline__ double power_lambda(const double *G, int S, int n, double *v, double *red,
+                                               const double *v0 = nullptr)
 {
     __syncthreads();
     if constexpr (NP >= 128) {
-        return power_lambda_block<NP>(G, S, n, v, red);
+        return power_lambda_block<NP>(G, S, n, v, red, v0);
     } else {
         if (threadIdx.x < 64) {
-            const double lam = power_lambda_regs<NP>(G, S, n, v);
+            const double lam = power_lambda_regs<NP>(G, S, n, v, v0);
             if (threadIdx.x == 0) red[15] = lam;
         }
         __syncthreads();
@@ -649,8 +652,36 @@ __device__ __forceinline__ void chol_body(const Problem &p, const Work &w, const
             Gn = w.Ge;
         }
         if (sp.shift_mode == SCQR_SHIFT_FRO) return trn;
-        const double lam = power_lambda<NP>(Gn, S, n, vbuf, red);
+        // Start vector: after a pass that ran this iteration, R~ v of that pass's last iterate v.
+        // Its Gram A' = R~^{-T} A R~^{-1} = I - s (R~ R~^T)^{-1} (with R~^T R~ = A + s I) has the
+        // eigenvectors R~ w of A's eigenvectors w, the largest eigenvalue on the largest of A's,
+        // so R~ v starts near the dominant eigenvector; the iteration then stops after a few steps
+        // where 1/sqrt(n) needs many on the clustered spectrum near 1.  Any start gives a lower
+        // bound of lambda_max.
+        const double *v0 = nullptr;
+        if (!obl_first && pass > 1 && ctl->vprev_pass == pass - 1) {
+            const double *Rp = factor_of(w, NP, pass - 1);
+            double ss = 0.0;
+            for (int i = threadIdx.x; i < NP; i += blockDim.x) {
+                double a = 0.0;
+                if (i < n)
+                    for (int j = i; j < n; ++j) a = __builtin_fma(Rp[i * NP + j], w.vprev[j], a);
+                ybuf[i] = a;
+                ss += a * a;
+            }
+            ss = block_sum(ss, red);
+            if (ss > 0.0 && isfinite(ss)) {
+                const double inv = 1.0 / sqrt(ss);
+                for (int i = threadIdx.x; i < NP; i += blockDim.x) ybuf[i] *= inv;
+                __syncthreads();
+                v0 = ybuf;
+            }
+        }
+        const double lam = power_lambda<NP>(Gn, S, n, vbuf, red, v0);
         if (!(lam >= 0.0)) return trn;
+        // keep the last iterate for the next pass's start
+        for (int i = threadIdx.x; i < n; i += blockDim.x) w.vprev[i] = vbuf[i];
+        if (threadIdx.x == 0) ctl->vprev_pass = pass;
         double dmax = 0.0;
         for (int i = 0; i < n; ++i) dmax = Gn[i * S + i] > dmax ? Gn[i * S + i] : dmax;
         return lam > dmax ? lam : dmax;
@@ -800,6 +831,7 @@ __device__ __forceinline__ void init_body(Ctl *ctl, scqr_info *info)
         ctl->status = SCQR_E_NOT_CONVERGED;
         ctl->f32_pass = 0;
         ctl->bad_b = 0;
+        ctl->vprev_pass = 0;
         ctl->bnorm = 1.0;
     }
     if (info) {

@@ -86,7 +86,7 @@ struct Ctl {
     int32_t status;
     int32_t f32_pass;   // FP32-first: pass 1 factor came from the binary32 Gram
     int32_t bad_b;      // a Gram kernel met an out-of-range index of a CSR B
-    int32_t pad;
+    int32_t vprev_pass; // pass whose power-iteration vector is in Work::vprev (0: none)
     double bnorm;       // ||B||_2 bound (1 for B = I)
 };
 
@@ -124,6 +124,7 @@ struct Work {
     double *gsum;       // parts_elems: the reduced Gram tiles of the last reduction
     double *bmax;       // nwg per-workgroup Gershgorin maxima (oblique first pass)
     double *Rsplit;     // np = 256: R~_11, R~_22 (128 x 128 each) and their reciprocal diagonals
+    double *vprev;      // np: the last power-iteration vector (start of the next pass's one)
     int nwg;            // workgroups (= partial count) of the pass kernels
     int nlvl2;          // level-2 partial count
     int64_t parts_elems;  // elements of one partial (tiles * 256, doubled for oblique pass 1)
