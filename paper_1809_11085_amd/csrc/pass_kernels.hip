@@ -164,6 +164,10 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
     // buffer accesses return zeros (loads) or are dropped (stores) past the end of the matrix,
     // and padding columns (cl >= n) use an offset outside the resource.
     double2 pre[PP];
+    // a single problem's pass streams X and Q once (non-temporal: measured 0.90 -> 0.87 ms for the
+    // fused pass and 0.42 -> 0.35 ms for the first Gram at 2^22 x 64); a batch's small instances
+    // may stay cached from one pass to the next
+    constexpr int CPOL = BATCH ? 0 : kBufStream;
     const int cl = 2 * (lane % (NP / 2)), rl = lane / (NP / 2);
     constexpr int RSTEP = 128 / NP;
     const uint32_t offx = cl < n ? (uint32_t)((rl * p.ldx + cl) * 8) : kBufOut;
@@ -173,7 +177,7 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
         if constexpr (VEC) {
             const __amdgpu_buffer_rsrc_t rs = rows_rsrc(p.X, p.ldx, rb, p.m, n);
 #pragma unroll
-            for (int i = 0; i < PP; ++i) pre[i] = buf_load2(rs, offx + (uint32_t)i * dxs);
+            for (int i = 0; i < PP; ++i) pre[i] = buf_load2<CPOL>(rs, offx + (uint32_t)i * dxs);
             return;
         }
 #pragma unroll
@@ -335,7 +339,7 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
                     const uint32_t dqs = (uint32_t)(RSTEP * p.ldq * 8);
 #pragma unroll
                     for (int i = 0; i < PP; ++i)
-                        buf_store2(rq, offq + (uint32_t)i * dqs,
+                        buf_store2<CPOL>(rq, offq + (uint32_t)i * dqs,
                                    *reinterpret_cast<const double2 *>(P + (rl + RSTEP * i) * S + cl));
                 } else {
 #pragma unroll
@@ -488,7 +492,7 @@ struct WideProd {
     int n2;            // 1 .. 128
 };
 
-template <int NP, int MODE, bool VEC>
+template <int NP, int MODE, bool VEC, bool NTC = false>
 __device__ __forceinline__ void
 pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__restrict__ Rt,
                const double *__restrict__ dinv, double *__restrict__ part_out,
@@ -585,7 +589,8 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
                 const bool ok = row < p.m && c < n;
                 const int64_t rr = row < p.m ? row : p.m - 1;
                 const int cc = c < n ? c : 0;
-                const d2 v = *reinterpret_cast<gview<const d2>>(as_global(p.X) + rr * p.ldx + cc);
+                const gview<const d2> src = reinterpret_cast<gview<const d2>>(as_global(p.X) + rr * p.ldx + cc);
+                const d2 v = NTC ? __builtin_nontemporal_load(src) : *src;
                 pre[i] = ok ? make_double2(v.x, v.y) : make_double2(0.0, 0.0);
             } else {
                 double a = 0.0, b = 0.0;
@@ -708,7 +713,10 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
                 const double2 v = *reinterpret_cast<const double2 *>(P + r * S + c);
                 const gview<double> dst = as_global(Qout) + row * p.ldq + c;
                 if (VEC) {
-                    *reinterpret_cast<gview<d2>>(dst) = (d2){v.x, v.y};
+                    if (NTC)
+                        __builtin_nontemporal_store((d2){v.x, v.y}, reinterpret_cast<gview<d2>>(dst));
+                    else
+                        *reinterpret_cast<gview<d2>>(dst) = (d2){v.x, v.y};
                 } else {
                     dst[0] = v.x;
                     if (c + 1 < n) dst[1] = v.y;
@@ -772,8 +780,9 @@ k_pass_wide(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
     const int64_t per = (npanels + gridDim.x - 1) / gridDim.x;
     const int64_t p0 = (int64_t)blockIdx.x * per;
     const int64_t p1 = (p0 + per < npanels) ? p0 + per : npanels;
-    pass_wide_body<NP, MODE, VEC>(p, Qout, Rt, dinv, partials + (int64_t)blockIdx.x * E, ctl, pass, final_gram,
-                                  p0 < p1 ? p0 : p1, p1);
+    // one problem: X and Q are streamed once per pass (non-temporal accesses)
+    pass_wide_body<NP, MODE, VEC, true>(p, Qout, Rt, dinv, partials + (int64_t)blockIdx.x * E, ctl, pass,
+                                        final_gram, p0 < p1 ? p0 : p1, p1);
 }
 
 // MODE 4 (NP = 128): the first half of the n = 256 block solve with the product for the second.
@@ -786,7 +795,7 @@ k_pass_wide4(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt
     const int64_t per = (npanels + gridDim.x - 1) / gridDim.x;
     const int64_t p0 = (int64_t)blockIdx.x * per;
     const int64_t p1 = (p0 + per < npanels) ? p0 + per : npanels;
-    pass_wide_body<128, 4, VEC>(p, Qout, Rt, dinv, nullptr, ctl, pass, 0, p0 < p1 ? p0 : p1, p1, pr);
+    pass_wide_body<128, 4, VEC, true>(p, Qout, Rt, dinv, nullptr, ctl, pass, 0, p0 < p1 ? p0 : p1, p1, pr);
 }
 
 

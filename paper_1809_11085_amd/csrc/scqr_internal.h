@@ -185,13 +185,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const double *base, 
     const int32_t nrec = rem > 0x7fffffff ? 0x7fffffff : (int32_t)rem;
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(base + r0 * ld), (short)0, nrec, 0x00020000);
 }
+// AUX: cache policy of the access (0: default; kBufStream: non-temporal, for data that a
+// kernel streams once and that is not read again before the kernel ends).
+constexpr int kBufStream = 2;
+template <int AUX = 0>
 __device__ __forceinline__ double2 buf_load2(__amdgpu_buffer_rsrc_t r, uint32_t off)
 {
-    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, AUX));
 }
+template <int AUX = 0>
 __device__ __forceinline__ void buf_store2(__amdgpu_buffer_rsrc_t r, uint32_t off, double2 v)
 {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, AUX);
 }
 
 // A trivially copyable descriptor loaded as 8-byte words through a constant view.
