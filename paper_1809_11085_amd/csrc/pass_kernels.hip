@@ -164,10 +164,9 @@ k_pass_tile(Problem p, double *__restrict__ Qout, const double *__restrict__ Rt,
     // buffer accesses return zeros (loads) or are dropped (stores) past the end of the matrix,
     // and padding columns (cl >= n) use an offset outside the resource.
     double2 pre[PP];
-    // a single problem's pass streams X and Q once (non-temporal: measured 0.90 -> 0.87 ms for the
-    // fused pass and 0.42 -> 0.35 ms for the first Gram at 2^22 x 64); a batch's small instances
-    // may stay cached from one pass to the next
-    constexpr int CPOL = BATCH ? 0 : kBufStream;
+    // a pass streams X and Q once (non-temporal: measured 0.90 -> 0.86 ms for the fused pass and
+    // 0.42 -> 0.34 ms for the first Gram at 2^22 x 64; the c4 batch 66-67 -> 63.5 ms)
+    constexpr int CPOL = kBufStream;
     const int cl = 2 * (lane % (NP / 2)), rl = lane / (NP / 2);
     constexpr int RSTEP = 128 / NP;
     const uint32_t offx = cl < n ? (uint32_t)((rl * p.ldx + cl) * 8) : kBufOut;
@@ -813,7 +812,7 @@ k_pass_wide_b(const BatchInst *__restrict__ insts, const BatchTask *__restrict__
         p.X = p.Q;
         p.ldx = p.ldq;
     }
-    pass_wide_body<NP, MODE, VEC>(p, p.Q, factor_of(I.w, NP, pass), dinv_of(I.w, NP, pass),
+    pass_wide_body<NP, MODE, VEC, true>(p, p.Q, factor_of(I.w, NP, pass), dinv_of(I.w, NP, pass),
                                   partials + (int64_t)blockIdx.x * E, I.w.ctl, pass, final_gram, t.r0 / 64,
                                   (t.r1 + 63) / 64);
 }
