@@ -585,12 +585,12 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
             const int r = e2 / (NP / 2), c = 2 * (e2 % (NP / 2));
             const int64_t row = rb + r;
             if (VEC) {
-                const bool ok = row < p.m && c < n;
-                const int64_t rr = row < p.m ? row : p.m - 1;
-                const int cc = c < n ? c : 0;
-                const gview<const d2> src = reinterpret_cast<gview<const d2>>(as_global(p.X) + rr * p.ldx + cc);
-                const d2 v = NTC ? __builtin_nontemporal_load(src) : *src;
-                pre[i] = ok ? make_double2(v.x, v.y) : make_double2(0.0, 0.0);
+                // buffer loads: rows past the end of the matrix read zeros, padding columns use an
+                // offset outside the resource (zeros as well)
+                const __amdgpu_buffer_rsrc_t rs = rows_rsrc(p.X, p.ldx, rb, p.m, n);
+                const uint32_t off = c < n ? (uint32_t)((r * p.ldx + c) * 8) : kBufOut;
+                pre[i] = buf_load2<NTC ? kBufStream : 0>(rs, off);
+                (void)row;
             } else {
                 double a = 0.0, b = 0.0;
                 if (row < p.m) {
@@ -605,14 +605,14 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
     if (p0 < p1) load_panel(p0);
     for (int64_t pn = p0; pn < p1; ++pn) {
         const int64_t r0 = pn * PR;
-        __syncthreads();  // the previous panel is no longer read
+        lds_barrier();  // the previous panel is no longer read
 #pragma unroll
         for (int i = 0; i < PP; ++i) {
             const int e2 = threadIdx.x + WAVES * 64 * i;
             const int r = e2 / (NP / 2), c = 2 * (e2 % (NP / 2));
             *reinterpret_cast<double2 *>(P + r * S + c) = pre[i];
         }
-        __syncthreads();
+        lds_barrier();
         load_x2(pn);
         if (pn + 1 < p1) load_panel(pn + 1);
 
@@ -700,7 +700,7 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
             for (int r = 0; r < 4; ++r) blk[4 * r * S] = d[r] * dj;
             wave_sync();
         }
-        __syncthreads();
+        lds_barrier();
 
         // ---- Q panel -> HBM
 #pragma unroll
@@ -708,18 +708,16 @@ pass_wide_body(const Problem &p, double *__restrict__ Qout, const double *__rest
             const int e2 = threadIdx.x + WAVES * 64 * i;
             const int r = e2 / (NP / 2), c = 2 * (e2 % (NP / 2));
             const int64_t row = r0 + r;
-            if (row < p.m && c < n) {
+            if constexpr (VEC) {
+                // buffer stores: rows past the end and padding columns are dropped
+                const __amdgpu_buffer_rsrc_t rq = rows_rsrc(Qout, p.ldq, r0, p.m, n);
+                const uint32_t off = c < n ? (uint32_t)((r * p.ldq + c) * 8) : kBufOut;
+                buf_store2<NTC ? kBufStream : 0>(rq, off, *reinterpret_cast<const double2 *>(P + r * S + c));
+            } else if (row < p.m && c < n) {
                 const double2 v = *reinterpret_cast<const double2 *>(P + r * S + c);
                 const gview<double> dst = as_global(Qout) + row * p.ldq + c;
-                if (VEC) {
-                    if (NTC)
-                        __builtin_nontemporal_store((d2){v.x, v.y}, reinterpret_cast<gview<d2>>(dst));
-                    else
-                        *reinterpret_cast<gview<d2>>(dst) = (d2){v.x, v.y};
-                } else {
-                    dst[0] = v.x;
-                    if (c + 1 < n) dst[1] = v.y;
-                }
+                dst[0] = v.x;
+                if (c + 1 < n) dst[1] = v.y;
             }
         }
 
@@ -1946,7 +1944,8 @@ template <int NP>
 static hipError_t launch_wide(hipStream_t s, const Problem &p, const Work &w, int mode, int pass, int final_gram)
 {
     const bool vec = (reinterpret_cast<uintptr_t>(p.X) & 15) == 0 && (p.ldx & 1) == 0 &&
-                     (reinterpret_cast<uintptr_t>(p.Q) & 15) == 0 && (p.ldq & 1) == 0 && (p.n & 1) == 0;
+                     (reinterpret_cast<uintptr_t>(p.Q) & 15) == 0 && (p.ldq & 1) == 0 && (p.n & 1) == 0 &&
+                     p.ldx <= kBufMaxLd && p.ldq <= kBufMaxLd;
     dim3 grid(w.nwg), block(256);
     const double *Rt = factor_of(w, NP, pass), *dv = dinv_of(w, NP, pass);
     if (mode == 1 && vec)
@@ -2005,7 +2004,8 @@ static hipError_t launch_trsm_256(hipStream_t s, const Problem &p, const Work &w
     const double *R11 = w.Rsplit, *R22 = w.Rsplit + 128 * 128;
     const double *d11 = w.Rsplit + 2 * 128 * 128, *d22 = d11 + 128;
     const bool vec = (reinterpret_cast<uintptr_t>(p.X) & 15) == 0 && (p.ldx & 1) == 0 &&
-                     (reinterpret_cast<uintptr_t>(p.Q) & 15) == 0 && (p.ldq & 1) == 0 && (p.n & 1) == 0;
+                     (reinterpret_cast<uintptr_t>(p.Q) & 15) == 0 && (p.ldq & 1) == 0 && (p.n & 1) == 0 &&
+                     p.ldx <= kBufMaxLd && p.ldq <= kBufMaxLd;
     const int cus = cu_count();
     Problem p1 = p;
     p1.n = 128;

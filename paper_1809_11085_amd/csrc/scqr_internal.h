@@ -185,6 +185,16 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const double *base, 
     const int32_t nrec = rem > 0x7fffffff ? 0x7fffffff : (int32_t)rem;
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(base + r0 * ld), (short)0, nrec, 0x00020000);
 }
+// Workgroup barrier that orders LDS accesses only.  Global loads and stores in flight stay in
+// flight across it; __syncthreads() also orders global memory and therefore waits for every
+// outstanding global access (on gfx950 loads and stores share one counter).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // AUX: cache policy of the access (0: default; kBufStream: non-temporal, for data that a
 // kernel streams once and that is not read again before the kernel ends).
 constexpr int kBufStream = 2;
