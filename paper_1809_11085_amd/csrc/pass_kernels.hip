@@ -1589,10 +1589,20 @@ k_gram_csr(Problem p, double *__restrict__ partials, double *__restrict__ bmax, 
     const int n = p.n;
     const int64_t m = p.m;
     const int r = threadIdx.x / TR, tc = threadIdx.x % TR;
+    // Panels, XCD by XCD: workgroups are dispatched round-robin over the chip's 8 XCDs
+    // (workgroup b on XCD b % 8), each with its own L2.  Each XCD gets a contiguous range of
+    // panels, and its workgroups take that range's panels in turn, so that the workgroups of
+    // one L2 work on neighbouring panels at the same time and the rows of X that a stencil's
+    // entries gather (the panel's neighbouring rows, shared by nearby panels) are fetched into
+    // that L2 once rather than by every workgroup that needs them.
     const int64_t npanels = (m + PR - 1) / PR;
-    const int64_t per = (npanels + gridDim.x - 1) / gridDim.x;
-    const int64_t p0 = (int64_t)blockIdx.x * per;
-    const int64_t p1 = (p0 + per < npanels) ? p0 + per : npanels;
+    const int G = gridDim.x;
+    const int nx = G < 8 ? G : 8;
+    const int xg = blockIdx.x % nx, slot = blockIdx.x / nx;
+    const int nslot = (G - xg + nx - 1) / nx;  // workgroups on this workgroup's XCD
+    const int64_t per = (npanels + nx - 1) / nx;
+    const int64_t p0 = (int64_t)xg * per + slot;
+    const int64_t p1 = ((int64_t)xg + 1) * per < npanels ? ((int64_t)xg + 1) * per : npanels;
 
     d4 acc[TPW];
 #pragma unroll
@@ -1608,7 +1618,7 @@ k_gram_csr(Problem p, double *__restrict__ partials, double *__restrict__ bmax, 
     bool bad = false;
     double bm = 0.0;
 
-    for (int64_t pn = p0; pn < p1; ++pn) {
+    for (int64_t pn = p0; pn < p1; pn += nslot) {
         const int64_t r0 = pn * PR;
         const int nr = (int)((m - r0 < PR) ? m - r0 : PR);
         __syncthreads();
