@@ -1573,7 +1573,8 @@ k_gram_csr(Problem p, double *__restrict__ partials, double *__restrict__ bmax, 
     constexpr int NTHR = WAVES * 64;
     constexpr int TR = NTHR / PR;      // threads per row of Y
     constexpr int CPT = NP / TR;       // columns per thread
-    constexpr int GB = NP == 256 ? 1 : (CPT >= 8 ? 2 : 4);  // entries whose loads are issued together
+    // entries whose loads are issued together, CPT loads each
+    constexpr int GB = NP == 256 ? 1 : (CPT >= 8 || (CPT == 4 && NP <= 64) ? 2 : 4);
     static_assert(NTHR % PR == 0 && CPT >= 1 && NP % TR == 0, "Y splits evenly over the threads");
     __shared__ double xs[PR * S], ys[PR * S];
     __shared__ double sval[CSR_CHUNK];
@@ -2041,13 +2042,14 @@ static hipError_t launch_trsm_256(hipStream_t s, const Problem &p, const Work &w
     return hipGetLastError();
 }
 
-// Waves per workgroup of the CSR Gram: 4 at n <= 16 (one column per thread), 8 up to n = 128;
-// at n = 256 the 136 tiles take 16 waves (9 tiles, 72 accumulator registers each), and the
-// first pass's two sets of tiles take two launches (KIND 2, then 3).
+// Waves per workgroup of the CSR Gram: 4 up to n = 64 (five workgroups per CU: each one's
+// staging barriers stall fewer waves; 27-point B at 10^6 x 64: 1.32 -> 1.15 ms per pass), 8 at
+// n = 128; at n = 256 the 136 tiles take 16 waves (9 tiles, 72 accumulator registers each), and
+// the first pass's two sets of tiles take two launches (KIND 2, then 3).
 template <int NP>
 static hipError_t launch_gram_csr(hipStream_t s, const Problem &p, const Work &w, int pass, bool euc, int final_gram)
 {
-    constexpr int W = NP <= 16 ? 4 : (NP == 256 ? 16 : 8);
+    constexpr int W = NP <= 64 ? 4 : (NP == 256 ? 16 : 8);
     dim3 grid(w.nwg), block(W * 64);
     if (euc) {
         if constexpr (NP == 256) {
