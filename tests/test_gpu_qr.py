@@ -422,3 +422,46 @@ def test_retried_pass_norm_estimate_is_tight(scqr, m, n):
             assert info.norm2sq[p] >= lam * (1 - 1e-6), (p, info.norm2sq[p], lam)
             checked += 1
     assert checked >= 1
+
+
+@pytest.mark.parametrize("n,kappa", [(1, 1.0), (16, 1e6), (33, 1e5), (64, 1e6), (100, 1e4), (128, 1e6),
+                                     (256, 1e5)])
+def test_square_matrix(scqr, n, kappa):
+    # m = n: the smallest problem the method takes (one panel, ragged for n not a multiple of 16)
+    X = synth.randsvd(n, n, kappa, seed=synth.seed_for(7, n))
+    Q, R, info = scqr.qr(dev(X), schedule="adaptive")
+    assert info.status == scqr.OK, info
+    Qh, Rh = host(Q), host(R)
+    assert accuracy.orthogonality(Qh)[0] <= 1e-13
+    assert accuracy.residual(X, Qh, Rh) <= 1e-13
+    assert np.all(np.diag(Rh) > 0) and np.all(np.tril(Rh, -1) == 0)
+    ro = oracle.scqr(X, schedule=oracle.ADAPTIVE)
+    assert ro.status == oracle.OK and ro.passes == info.passes
+    assert np.linalg.norm(Rh - ro.R) <= 1e-10 * np.linalg.norm(ro.R)
+    assert np.max(np.abs(Qh - ro.Q)) <= 1e-10
+
+
+@pytest.mark.parametrize("n,pad,oblique", [(16, 3, False), (64, 3, False), (64, 4, False), (100, 5, False),
+                                           (128, 3, False), (128, 6, False), (256, 2, False),
+                                           (64, 3, True), (128, 4, True)])
+def test_strided_input(scqr, n, pad, oblique):
+    # X as columns [c0, c0 + n) of an m x (n + pad) matrix, leading dimension n + pad: odd pads
+    # start X 8 bytes into a row (unpaired loads), even pads 16 bytes in (paired loads for even
+    # n); the factorization must equal that of the contiguous copy bit for bit
+    m = 20011
+    Xh = synth.randsvd(m, n, 1e12, seed=synth.seed_for(7, 3 * n + pad))
+    B = None
+    if oblique:
+        d, o = synth.tridiag_b(m, seed=synth.seed_for(7, 5))
+        B = (dev(d), dev(o))
+    Qc, Rc, ic = scqr.qr(dev(Xh), B=B)
+    assert ic.status == scqr.OK
+    W = torch.full((m, n + pad), float("nan"), dtype=torch.float64, device="cuda")
+    c0 = 1 if pad % 2 else 2
+    W[:, c0:c0 + n] = dev(Xh)
+    Q, R, info = scqr.qr(W[:, c0:c0 + n], B=B)
+    assert info.status == scqr.OK and info.passes == ic.passes
+    assert torch.equal(Q, Qc) and torch.equal(R, Rc)
+    # the padding columns are neither read into the result nor written
+    assert torch.isnan(W[:, :c0]).all() and torch.isnan(W[:, c0 + n:]).all()
+    np.testing.assert_array_equal(host(W[:, c0:c0 + n]), Xh)
