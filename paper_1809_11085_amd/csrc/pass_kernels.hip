@@ -443,11 +443,37 @@ __device__ __forceinline__ double row_bcast(double v)
 // broadcast along the lane's row and column j takes -t_K c[K] (c = r_Kj / r_KK for the columns
 // K still updates, 0 elsewhere).  FWD runs K = 0, 1, ..., 15, otherwise K = 15, ..., 0.  The
 // reciprocal diagonal is applied by the caller after the last step.
+// The first step is left to the compiler: its inputs come from MFMAs, whose read-after-write
+// waits the compiler inserts.  Every later step reads values the previous step wrote on the VALU
+// and takes the broadcast as a DPP operand of v_fmac_f64 (d -= bcast(d) c in one instruction with
+// one rounding, the same value as the separate broadcast and FMA), after the two wait states a
+// DPP read of a VALU result needs.
+template <int K>
+__device__ __forceinline__ void diag_step_dpp(d4 &d, double c)
+{
+    double a0 = d[0], a1 = d[1], a2 = d[2], a3 = d[3];
+    asm volatile("s_nop 1\n\t"
+                 "v_fmac_f64_dpp %0, -%0, %4 row_newbcast:%5 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %1, -%1, %4 row_newbcast:%5 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %2, -%2, %4 row_newbcast:%5 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %3, -%3, %4 row_newbcast:%5 row_mask:0xf bank_mask:0xf"
+                 : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3)
+                 : "v"(c), "i"(K));
+    d[0] = a0;
+    d[1] = a1;
+    d[2] = a2;
+    d[3] = a3;
+}
+
 template <int K, bool FWD>
 __device__ __forceinline__ void diag_solve_steps(d4 &d, const double (&c)[16])
 {
+    if constexpr (K == (FWD ? 0 : 15)) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) d[r] = __builtin_fma(-row_bcast<K>(d[r]), c[K], d[r]);
+        for (int r = 0; r < 4; ++r) d[r] = __builtin_fma(-row_bcast<K>(d[r]), c[K], d[r]);
+    } else {
+        diag_step_dpp<K>(d, c[K]);
+    }
     if constexpr (FWD && K < 15) diag_solve_steps<K + 1, FWD>(d, c);
     if constexpr (!FWD && K > 0) diag_solve_steps<K - 1, FWD>(d, c);
 }
